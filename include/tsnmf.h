@@ -1,0 +1,256 @@
+/*
+ * tsnmf.h - C ABI of libtsnmf: single-pass tall-and-skinny QR (R factor only),
+ * Gaussian projection, and the n x n steps of near-separable NMF on MI355X.
+ *
+ * Method: Benson, Lee, Rajwa, Gleich, "Scalable methods for nonnegative matrix
+ * factorizations of near-separable tall-and-skinny matrices".  For X (m x n,
+ * m >> n, X >= 0) the extreme columns of X are those of the n x n factor R of
+ * the thin QR X = QR (Sec. 2.2), H is found by NNLS on R (Sec. 2.4), the
+ * column l1 norms D are accumulated in the same pass so that X D^{-1} can be
+ * handled as R D^{-1} (Sec. 3.3), and G^T X with Gaussian G is the alternative
+ * projection (Sec. 2.3, Sec. 3.2 / Algorithm 1).
+ *
+ * Conventions shared by every call
+ *   - Matrix/vector arguments are DEVICE pointers owned by the caller, except
+ *     where a comment says "host".  The library never frees or keeps them
+ *     beyond the completion of the work it enqueued.
+ *   - Every compute call is stream-ordered and asynchronous: it enqueues work on
+ *     `stream` (NULL = the null stream) and returns; results are valid once the
+ *     stream has reached that point.
+ *   - Return value: 0 on success; -i if the i-th argument is invalid (checked on
+ *     the host before anything is enqueued); a positive TSNMF_ERR_* code for a
+ *     runtime failure (for TSNMF_ERR_HIP, tsnmf_last_hip_error() gives the HIP
+ *     error code).
+ *   - Numerical outcomes (early stop, iteration caps) are reported through
+ *     optional device `info` outputs, never through host synchronisation.
+ *   - NaN or Inf in the input propagates into the outputs; it is not trapped.
+ *   - Outputs are column-major; index sets are 0-based int32.
+ *   - The library keeps one grow-only device workspace per device.  It is
+ *     allocated on first use (or by tsnmf_reserve); a call made while `stream`
+ *     is being captured into a graph returns TSNMF_ERR_CAPTURE instead of
+ *     allocating, so reserve before capturing.
+ *   - Calls that share the workspace must not run concurrently on different
+ *     streams of the same device.
+ */
+#ifndef TSNMF_H
+#define TSNMF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- flags ---------------------------------------------------------------- */
+#define TSNMF_F64          0x1u   /* input elements are IEEE binary64            */
+#define TSNMF_F32          0x2u   /* input elements are IEEE binary32            */
+#define TSNMF_BF16         0x4u   /* input elements are bfloat16                 */
+#define TSNMF_DTYPE_MASK   0x7u
+#define TSNMF_ROW_MAJOR    0x00u  /* X(i, j) at X[i * ld + j], ld >= n           */
+#define TSNMF_COL_MAJOR    0x10u  /* X(i, j) at X[i + j * ld], ld >= m           */
+#define TSNMF_LEAF_F64     0x20u  /* TSQR: factor row blocks in FP64 (default for
+                                     F64 input; for F32 input the values are
+                                     widened exactly and the whole path is FP64) */
+#define TSNMF_GP_MFMA_BF16 0x100u /* projection on matrix cores: G and X rounded
+                                     to bfloat16 (nearest-even), FP32 accumulate */
+#define TSNMF_GP_SIMD_F32  0x200u /* projection on the vector ALUs in FP32       */
+
+/* ---- status codes ----------------------------------------------------------- */
+#define TSNMF_OK               0
+#define TSNMF_ERR_HIP          1  /* a HIP runtime call failed                   */
+#define TSNMF_ERR_NOMEM        2  /* workspace allocation failed                 */
+#define TSNMF_ERR_CAPTURE      3  /* workspace too small while stream capturing   */
+#define TSNMF_ERR_UNSUPPORTED  4  /* shape outside the supported range            */
+
+#define TSNMF_MAX_N 128           /* largest column count of the TSQR / GP paths */
+
+/* ---- thin QR, R factor only ------------------------------------------------- */
+
+/*
+ * tsnmf_tsqr_r: R factor of the thin QR of X, and the l1 column sums of X, in
+ * one pass over X (Sec. 3.1 "TSQR and R-SVD": only R is formed, Q^T is applied
+ * implicitly; Sec. 3.3 "Column normalization": the column norms are
+ * accumulated in the same pass).
+ *
+ *   X       device, m x n, dtype and layout from `flags` (TSNMF_F32 or
+ *           TSNMF_F64; TSNMF_ROW_MAJOR or TSNMF_COL_MAJOR; TSNMF_LEAF_F64
+ *           optional).  Read exactly once.
+ *   m, n    1 <= n <= TSNMF_MAX_N, m >= 1.  (m < n is accepted: R is then the
+ *           n x n factor of X padded with zero rows.)
+ *   ld      leading dimension in elements (>= n row-major, >= m column-major).
+ *   R       device, n x n FP64, column-major (ldR = n), output: upper
+ *           triangular with R(i, i) >= 0 and exact zeros below the diagonal, so
+ *           that R^T R = X^T X.  Unique when X has full column rank.
+ *   colsum  device FP64[n] or NULL; output colsum[j] = sum_i |X(i, j)|.
+ *
+ * Row blocks are factored by Householder reflections in the input precision
+ * (FP32 for F32 input unless TSNMF_LEAF_F64), each workgroup keeping a running
+ * R for its contiguous slab of rows; the slab factors are combined by a tree
+ * of FP64 QR factorisations of stacked triangles.  The result is
+ * deterministic for a given (m, n, flags, configuration).
+ */
+int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
+                 double* R, double* colsum, hipStream_t stream);
+
+/* Launch geometry of the TSQR path.  Zero fields mean "library default". */
+typedef struct tsnmf_tsqr_config {
+    int64_t leaf_rows;      /* rows per workgroup slab (the TSQR leaf); rounded up
+                               to a whole number of row blocks                    */
+    int32_t tree_arity;     /* slab factors merged per tree node, 2..64          */
+    int32_t rows_per_lane;  /* row block height = 64 * rows_per_lane; 1..8        */
+} tsnmf_tsqr_config;
+
+/* As tsnmf_tsqr_r with an explicit configuration (`cfg` is a host pointer or
+   NULL).  Every configuration gives the same R up to rounding. */
+int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
+                    double* R, double* colsum, const tsnmf_tsqr_config* cfg,
+                    hipStream_t stream);
+
+/* ---- batched thin QR ---------------------------------------------------------- */
+
+/* One matrix of a batch (host struct; the pointers inside are device pointers). */
+typedef struct tsnmf_matrix_desc {
+    const void* X;    /* m x n, layout and dtype from the plan's flags            */
+    int64_t m, n, ld; /* as in tsnmf_tsqr_r                                       */
+    double* R;        /* n x n FP64 column-major output                           */
+    double* colsum;   /* FP64[n] output or NULL                                   */
+} tsnmf_matrix_desc;
+
+typedef struct tsnmf_batch_plan_s* tsnmf_batch_plan;
+
+/*
+ * tsnmf_batch_plan_create: validate a batch of independent TSQR problems of
+ * uneven m and n and build, on the device, the work list of one persistent
+ * launch (one item per row slab, longest-first) plus the per-matrix reduction
+ * trees.  Host call, synchronous, allocates; do it outside graph capture.
+ *   batch  number of matrices, 1..65536
+ *   desc   host array of `batch` descriptors
+ *   flags  TSNMF_F32 (FP32 row blocks, FP64 trees) with TSNMF_ROW_MAJOR
+ *   plan   host output handle
+ */
+int tsnmf_batch_plan_create(int32_t batch, const tsnmf_matrix_desc* desc, uint32_t flags,
+                            tsnmf_batch_plan* plan);
+
+/* Enqueue the whole batch: one persistent kernel over all row slabs of all
+   matrices, then the reduction trees and the finalisation of every R.  Makes no
+   allocation and no host synchronisation, so it can be captured into a HIP
+   graph and replayed; the X, R and colsum buffers named in the plan are used. */
+int tsnmf_tsqr_r_batched(tsnmf_batch_plan plan, hipStream_t stream);
+
+/* Free a plan (host call; the caller must ensure no enqueued use is pending). */
+int tsnmf_batch_plan_destroy(tsnmf_batch_plan plan);
+
+/* ---- Gaussian projection -------------------------------------------------------- */
+
+/*
+ * tsnmf_gauss_proj: Y = G^T X with G (m x k) i.i.d. N(0, 1), generated on the
+ * fly and never stored (Sec. 2.3; Sec. 3.2 Algorithm 1: each data row x_i
+ * contributes the outer product g_i x_i^T, partial sums are combined, then
+ * summed across workers).
+ *   X        device, m x n, TSNMF_F32 or TSNMF_BF16, row-major (ld >= n).
+ *   k        number of projected rows, multiple of 4, 4 <= k <= 4096.
+ *   seed     64-bit key of the generator.
+ *   row_offset  global index of X's first row (lets row shards of one matrix
+ *            use the rows of G they would use unsharded).
+ *   Y        device FP32, k x n column-major (ldY = k), output.
+ *   colsum   device FP64[n] or NULL: l1 column sums of X in the same pass.
+ *   flags    dtype | TSNMF_GP_MFMA_BF16 or TSNMF_GP_SIMD_F32 (BF16 input
+ *            requires MFMA; F32 input defaults to SIMD).
+ * G(i, l) is a fixed function of (seed, row_offset + i, l): Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
+ * (i mod 2^32, i >> 32, l / 4, 0) gives x0..x3; u_a = ((x_a >> 8) + 1) 2^-24;
+ * (G(i,4q), G(i,4q+1)) = sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1) and
+ * likewise (x2, x3) for columns 4q+2, 4q+3.  Independent of launch geometry.
+ */
+int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
+                     int32_t k, uint64_t seed, int64_t row_offset, float* Y,
+                     double* colsum, hipStream_t stream);
+
+/* ---- n x n steps (FP64, one workgroup each) --------------------------------------- */
+
+/*
+ * tsnmf_select_spa: Successive Projection Algorithm (Sec. 2.1) on
+ * M diag(1/colscale): r times pick j* = argmax_j ||Z(:, j)||_2^2 over columns
+ * not yet picked (ties -> smallest j), then Z <- Z - u (u^T Z) with
+ * u = Z(:, j*) / ||Z(:, j*)||.  Z starts as M diag(1/colscale).
+ *   M         device FP64, p x n column-major (ldm >= p), p, n in 1..TSNMF_MAX_N*2
+ *   colscale  device FP64[n] or NULL (no scaling); e.g. the colsum of tsnmf_tsqr_r
+ *   r         1..n picks
+ *   K         device int32[r] output, in selection order
+ *   score     device FP64[r] or NULL: the winning ||Z(:, j*)||^2 of each pick
+ *   info      device int32[1] output: number of columns picked (< r if the best
+ *             score reached exactly 0 first; remaining K entries are -1)
+ */
+int tsnmf_select_spa(const double* M, int32_t p, int32_t n, int32_t ldm,
+                     const double* colscale, int32_t r, int32_t* K, double* score,
+                     int32_t* info, hipStream_t stream);
+
+/*
+ * tsnmf_select_xray: greedy XRAY (Sec. 2.1): r times pick
+ * j* = argmax_j ||Res^T M(:, j)||_2 / ||M(:, j)||_2 over unpicked nonzero
+ * columns, then Res = M - M(:, K) H with H the NNLS fit of every column of M on
+ * the picked columns (Lawson-Hanson, as tsnmf_nnls).  Res starts as M.
+ *   M, p, n, ldm as in tsnmf_select_spa;  r in 1..min(n, 64)
+ *   K     device int32[r] output in selection order (-1 past an early stop)
+ *   info  device int32[1] output: number picked
+ */
+int tsnmf_select_xray(const double* M, int32_t p, int32_t n, int32_t ldm, int32_t r,
+                      int32_t* K, int32_t* info, hipStream_t stream);
+
+/*
+ * tsnmf_select_gp: Gaussian-projection selection (Sec. 2.3): for each row l of
+ * Y diag(1/colscale) the indices of the minimum and the maximum entries are
+ * added to K (ties -> smallest j); the distinct indices are ranked by how many
+ * rows chose them (descending), then by index, and the first r are returned.
+ *   Y         device FP32, k x n column-major (ldy >= k), e.g. tsnmf_gauss_proj
+ *   colscale  device FP64[n] or NULL
+ *   K         device int32[r] output (-1 past the number found)
+ *   counts    device int32[n] or NULL: selection count of every column
+ *   info      device int32[1] output: number of indices returned
+ */
+int tsnmf_select_gp(const float* Y, int32_t k, int32_t n, int32_t ldy, const double* colscale,
+                    int32_t r, int32_t* K, int32_t* counts, int32_t* info, hipStream_t stream);
+
+/*
+ * tsnmf_nnls: H(:, i) = argmin_{y >= 0} ||M(:, K) y - M(:, i)||_2^2 for every
+ * column i (Sec. 2.4; with M = R this equals the fit on X itself), by the
+ * Lawson-Hanson active-set method in FP64 (at most 3 r outer iterations).
+ *   M, p, n, ldm  device FP64 p x n column-major
+ *   K, r          device int32[r] column indices, 1 <= r <= min(n, 64)
+ *   H             device FP64 r x n column-major (ldh >= r) output
+ *   resid2        device FP64[n] or NULL: ||M(:, K) H(:, i) - M(:, i)||^2
+ *   info          device int32[n] or NULL: 1 where the iteration cap was hit
+ */
+int tsnmf_nnls(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t* K, int32_t r,
+               double* H, int32_t ldh, double* resid2, int32_t* info, hipStream_t stream);
+
+/*
+ * tsnmf_residual: relative residual ||M - M(:, K) H||_F^2 / ||M||_F^2 (Sec. 4's
+ * error measure; Sec. 2.4 shows it can be computed from R instead of X).
+ *   relerr  device FP64[1] output (0 when M = 0)
+ */
+int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t* K,
+                   int32_t r, const double* H, int32_t ldh, double* relerr, hipStream_t stream);
+
+/* ---- housekeeping ------------------------------------------------------------------- */
+
+/* Grow the current device's workspace so that TSQR calls with m <= max_m and
+   n <= max_n, and projections with k <= max_k, need no allocation (required
+   before graph capture).  Host call, synchronous. */
+int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
+
+/* Human-readable text of a return code (static storage). */
+const char* tsnmf_status_string(int status);
+
+/* HIP error code of the most recent TSNMF_ERR_HIP on the calling thread. */
+int tsnmf_last_hip_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int tsnmf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSNMF_H */

@@ -1,0 +1,133 @@
+// C entry points of libtsnmf: argument validation, workspace, status codes.
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tsnmf {
+
+namespace {
+thread_local int g_last_hip = 0;
+
+struct Workspace {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::vector<Workspace> g_ws;
+
+bool is_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+int grow(int dev, size_t bytes) {
+    Workspace& w = g_ws[dev];
+    if (w.bytes >= bytes) return TSNMF_OK;
+    // The old buffer may still be in use by enqueued work: drain the device first.
+    if (w.ptr != nullptr) {
+        TSNMF_HIP(hipDeviceSynchronize());
+        TSNMF_HIP(hipFree(w.ptr));
+        w.ptr = nullptr;
+        w.bytes = 0;
+    }
+    size_t sz = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        (void)hipGetLastError();
+        return TSNMF_ERR_NOMEM;
+    }
+    w.ptr = p;
+    w.bytes = sz;
+    return TSNMF_OK;
+}
+}  // namespace
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return TSNMF_ERR_HIP;
+}
+
+int workspace_get(size_t bytes, hipStream_t stream, void** out) {
+    int dev = 0;
+    TSNMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    if (g_ws[dev].bytes < bytes) {
+        if (is_capturing(stream)) return TSNMF_ERR_CAPTURE;
+        if (int st = grow(dev, bytes)) return st;
+    }
+    *out = g_ws[dev].ptr;
+    return TSNMF_OK;
+}
+
+int workspace_reserve(size_t bytes) {
+    int dev = 0;
+    TSNMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    return grow(dev, bytes);
+}
+
+}  // namespace tsnmf
+
+using namespace tsnmf;
+
+extern "C" {
+
+int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, double* R,
+                    double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream) {
+    if (X == nullptr) return -1;
+    if (m < 1) return -2;
+    if (n < 1) return -3;
+    const uint32_t dt = flags & TSNMF_DTYPE_MASK;
+    const bool col = (flags & TSNMF_COL_MAJOR) != 0;
+    if (ld < (col ? m : n)) return -4;
+    if ((dt != TSNMF_F32 && dt != TSNMF_F64) ||
+        (flags & ~(TSNMF_DTYPE_MASK | TSNMF_COL_MAJOR | TSNMF_LEAF_F64)) != 0)
+        return -5;
+    if (R == nullptr) return -6;
+    if (cfg != nullptr) {
+        if (cfg->leaf_rows < 0 || cfg->tree_arity < 0 || cfg->tree_arity == 1 || cfg->tree_arity > 64 ||
+            cfg->rows_per_lane < 0 || cfg->rows_per_lane > 8)
+            return -8;
+    }
+    if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
+    if (n > 32) return TSNMF_ERR_UNSUPPORTED;
+    return tsqr_r_impl(X, m, (int)n, ld, flags, R, colsum, cfg, stream);
+}
+
+int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, double* R,
+                 double* colsum, hipStream_t stream) {
+    return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, nullptr, stream);
+}
+
+int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
+    if (max_m < 0) return -1;
+    if (max_n < 0 || max_n > TSNMF_MAX_N) return -2;
+    if (max_k < 0 || max_k > 4096) return -3;
+    size_t b = 0;
+    if (max_m > 0 && max_n > 0) b = tsqr_workspace_bytes(max_m, max_n);
+    return workspace_reserve(b);
+}
+
+const char* tsnmf_status_string(int status) {
+    if (status < 0) return "invalid argument";
+    switch (status) {
+        case TSNMF_OK: return "success";
+        case TSNMF_ERR_HIP: return "HIP runtime error";
+        case TSNMF_ERR_NOMEM: return "workspace allocation failed";
+        case TSNMF_ERR_CAPTURE: return "workspace too small while the stream is capturing";
+        case TSNMF_ERR_UNSUPPORTED: return "unsupported shape";
+        default: return "unknown status";
+    }
+}
+
+int tsnmf_last_hip_error(void) { return g_last_hip; }
+
+int tsnmf_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+// Streaming Householder TSQR kernel for n <= 32 columns (one wave per slab).
+//
+// Each wave owns a contiguous slab of rows and keeps the n x n R factor of
+// all rows it has seen so far (Sec. 3.1: only R is formed).  It reads its slab
+// in row blocks of 64 * RPL rows -- lane L holds rows L, L + 64, ... of the
+// block, one register per (row, column) -- and folds each block into R with
+// the structured Householder QR of [R; B]: reflector j is [e_j; y] with
+// y = B(:, j) / (alpha - beta), so it touches row j of R and all block rows.
+// With d_k = B(:, j)^T B(:, k) (k >= j), sigma = d_j and alpha = R(j, j):
+//     beta = -sign(alpha) sqrt(alpha^2 + sigma),  tau = (beta - alpha) / beta,
+//     w_k  = R(j, k) + d_k / (alpha - beta)        (= v^T [R; B](:, k)),
+//     R(j, k) <- R(j, k) - tau w_k  (R(j, j) <- beta),
+//     B(:, k) <- B(:, k) + (1 / beta) B(:, j) w_k  (since tau / (alpha - beta) = -1 / beta).
+// All d_k of one step come from one reduce-scatter butterfly (wave.hpp), so
+// value k - j of step j lives in a fixed lane pattern; row j of R is stored in
+// LDS indexed by that value number, so the R update is one lane-parallel op.
+// The block's l1 column sums (Sec. 3.3) are reduced by one more butterfly and
+// accumulated in FP64.
+//
+// The same kernel, instantiated in FP64, combines the slab factors: the
+// stacked n x n partial R's of `group` slabs are just a taller input.
+#pragma once
+#include "wave.hpp"
+
+namespace tsnmf {
+
+enum LoadKind : int { LOAD_ROW = 0, LOAD_ROW_STAGED = 1, LOAD_COL = 2 };
+enum CsMode : int { CS_NONE = 0, CS_DATA = 1, CS_PARTIALS = 2 };
+
+struct StreamArgs {
+    const void* X;         // input of element type TI, rows [0, m)
+    int64_t m;             // rows
+    int64_t ld;            // leading dimension (elements)
+    int64_t slab;          // rows per stream
+    int64_t nstreams;      // streams (one wave each)
+    int32_t load;          // LoadKind
+    int32_t cs_mode;       // CsMode
+    const double* in_cs;   // CS_PARTIALS: [nin][n] partial column sums
+    int64_t nin;           // CS_PARTIALS: number of input partials
+    int32_t group;         // CS_PARTIALS: partials summed per stream
+    int32_t pad_;
+    double* out_R;         // [nstreams][n][n] row-major, zeros below diagonal
+    double* out_cs;        // [nstreams][n] (CS_DATA / CS_PARTIALS)
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T> __device__ __forceinline__ T rcp_fast(T x);
+template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float abs_t(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double abs_t(double a) { return __builtin_fabs(a); }
+template <typename T> __device__ __forceinline__ T sqrt_t(T x);
+template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return __builtin_sqrtf(x); }
+template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return __builtin_sqrt(x); }
+
+template <typename T, typename TI, int N, int RPL> struct Small {
+    static_assert(N >= 1 && N <= 32, "small kernel covers 1..32 columns");
+    static constexpr int BR = 64 * RPL;                   // rows per block
+    static constexpr int PN = ilog2(pow2ceil(N));         // butterfly order of n values
+    static constexpr int roff(int j) {
+        int o = 0;
+        for (int t = 0; t < j; ++t) o += pow2ceil(N - t);
+        return o;
+    }
+    static constexpr int RS = roff(N);                    // R slots per wave (elements of T)
+    static constexpr int SS = (N % 2) ? N : N + 1;        // staging row stride, odd -> no bank conflicts
+    static constexpr int STG = 64 * SS;                   // staging elements (TI) per wave
+    static constexpr size_t r_bytes() { return (size_t)4 * RS * sizeof(T); }
+    static constexpr size_t lds_bytes(bool staged) {  // per workgroup of 4 waves
+        return ((r_bytes() + 15) & ~(size_t)15) + (staged ? (size_t)4 * STG * sizeof(TI) : 0);
+    }
+
+    // ---- one Householder step (column J) -------------------------------------
+    template <int J> static __device__ __forceinline__ void step(T (&x)[RPL][N], T* Rl) {
+        if constexpr (J < N) {
+            constexpr int CNT = N - J;
+            constexpr int V = pow2ceil(CNT);
+            constexpr int P = ilog2(V);
+            const int L = lane_id();
+            T p[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (v < CNT) {
+                    T s = x[0][J] * x[0][J + v];
+#pragma unroll
+                    for (int r = 1; r < RPL; ++r) s = fma_t(x[r][J], x[r][J + v], s);
+                    p[v] = s;
+                } else {
+                    p[v] = T(0);
+                }
+            }
+            const T D = butterfly<P>(p);             // lane L: d_{J + vidx(L)}
+            const int vi = bfly_vidx<P>(L);
+            T* row = Rl + roff(J);
+            const T rj = row[vi];                    // R(J, J + vi), zero in padding slots
+            const T sigma = lane_bcast(D, 0);
+            const T alpha = lane_bcast(rj, 0);
+            const T nrm = sqrt_t<T>(fma_t(alpha, alpha, sigma));
+            const bool live = sigma != T(0);
+            const T beta = live ? (alpha >= T(0) ? -nrm : nrm) : alpha;
+            const T inv_beta = rcp_fast<T>(beta);
+            const T s = live ? rcp_fast<T>(alpha - beta) : T(0);        // 1 / (alpha - beta)
+            const T tau = live ? (beta - alpha) * inv_beta : T(0);
+            const T c = live ? inv_beta : T(0);                          // = -tau * s
+            const T w = fma_t(s, D, rj);
+            T rn = fma_t(-tau, w, rj);
+            if (vi == 0) rn = beta;
+            row[vi] = rn;
+            T t[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) t[r] = c * x[r][J];
+#pragma unroll
+            for (int v = 1; v < CNT; ++v) {
+                const T wk = lane_bcast(w, bfly_lane(v, P));
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
+            }
+            step<J + 1>(x, Rl);
+        }
+    }
+
+    // ---- load one block of rows [b0, min(b0 + BR, r1)) ---------------------------
+    template <int LOAD>
+    static __device__ __forceinline__ void load(T (&x)[RPL][N], const StreamArgs& a, int64_t b0,
+                                                int64_t r1, TI* St) {
+        const int L = lane_id();
+        const TI* X = (const TI*)a.X;
+        if constexpr (LOAD == LOAD_ROW_STAGED) {
+            // The block is contiguous (ld == N).  Read it with coalesced loads in
+            // memory order (register (r, c) <- element (r N + c) 64 + L), then
+            // turn each 64-row chunk into one row per lane through LDS.
+            static_assert(sizeof(T) == sizeof(TI), "staged load keeps the input type");
+            const TI* Xb = X + b0 * (int64_t)N + L;
+            const int valid = (int)((min(r1, b0 + (int64_t)BR) - b0) * N) - L;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    const int e = (r * N + c) * 64;
+                    x[r][c] = e < valid ? (T)__builtin_nontemporal_load(Xb + e) : T(0);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    const int el = c * 64 + L;            // element within this 64-row chunk
+                    St[(el / N) * SS + (el % N)] = (TI)x[r][c];
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int c = 0; c < N; ++c) x[r][c] = (T)St[L * SS + c];
+                wave_lds_sync();
+            }
+        } else if constexpr (LOAD == LOAD_COL) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t i = b0 + r * 64 + L;
+                const bool ok = i < r1;
+                const TI* Xi = X + i;
+#pragma unroll
+                for (int c = 0; c < N; ++c)
+                    x[r][c] = ok ? (T)__builtin_nontemporal_load(Xi + (int64_t)c * a.ld) : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t i = b0 + r * 64 + L;
+                const bool ok = i < r1;
+                const TI* Xi = X + i * a.ld;
+#pragma unroll
+                for (int c = 0; c < N; ++c) x[r][c] = ok ? (T)Xi[c] : T(0);
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void colsum_block(const T (&x)[RPL][N], double& acc) {
+        constexpr int V = 1 << PN;
+        T p[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            if (c < N) {
+                T s = abs_t(x[0][c]);
+#pragma unroll
+                for (int r = 1; r < RPL; ++r) s += abs_t(x[r][c]);
+                p[c] = s;
+            } else {
+                p[c] = T(0);
+            }
+        }
+        acc += (double)butterfly<PN>(p);
+    }
+};
+
+template <typename T, typename TI, int N, int RPL, int LOAD>
+__global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
+    using S = Small<T, TI, N, RPL>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wv = (int)(threadIdx.x >> 6);
+    const int L = lane_id();
+    const int64_t sid = (int64_t)blockIdx.x * 4 + wv;
+    if (sid >= a.nstreams) return;                      // whole wave; no block barriers used
+    T* Rl = (T*)smem + wv * S::RS;
+    TI* St = (TI*)(smem + ((S::r_bytes() + 15) & ~(size_t)15)) + wv * S::STG;
+
+    for (int i = L; i < S::RS; i += 64) Rl[i] = T(0);
+    wave_lds_sync();
+
+    const int64_t r0 = sid * a.slab;
+    const int64_t r1 = min(a.m, r0 + a.slab);
+    double acc = 0.0;
+    for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
+        T x[RPL][N];
+        S::template load<LOAD>(x, a, b0, r1, St);
+        if (a.cs_mode == CS_DATA) S::colsum_block(x, acc);
+        S::template step<0>(x, Rl);
+    }
+    wave_lds_sync();
+
+    // Partial R, row-major with explicit zeros below the diagonal.
+    double* out = a.out_R + sid * (int64_t)N * N;
+    int off = 0;
+    for (int j = 0; j < N; ++j) {
+        if (L < N) out[j * N + L] = L >= j ? (double)Rl[off + (L - j)] : 0.0;
+        off += pow2ceil(N - j);
+    }
+    if (a.cs_mode == CS_DATA) {
+        int src = 0;                                    // lane holding column L's sum
+        for (int s2 = 0; s2 < S::PN; ++s2) src |= ((L >> s2) & 1) << (5 - s2);
+        const double v = lane_gather(acc, src);
+        if (L < N) a.out_cs[sid * N + L] = v;
+    } else if (a.cs_mode == CS_PARTIALS) {
+        if (L < N) {
+            double s = 0.0;
+            for (int t = 0; t < a.group; ++t) {
+                const int64_t idx = sid * a.group + t;
+                if (idx < a.nin) s += a.in_cs[idx * N + L];
+            }
+            a.out_cs[sid * N + L] = s;
+        }
+    }
+}
+
+}  // namespace tsnmf

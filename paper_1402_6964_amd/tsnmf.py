@@ -1,0 +1,284 @@
+"""Python binding of libtsnmf (ctypes; argument marshalling only).
+
+The functions named like the C entry points (``tsnmf_tsqr_r`` ...) take
+torch tensors or raw device addresses and forward them unchanged; every step of
+the computation runs in the HIP library.  The convenience wrappers below them
+(``tsqr_r`` ...) only allocate outputs with torch and pick flags.
+
+Importing this module loads the in-tree ``libtsnmf.so``; it raises if the
+library is missing, so there is no silent fallback.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtsnmf.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1402_6964_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- flags (mirror include/tsnmf.h) ---------------------------------------------
+F64 = 0x1
+F32 = 0x2
+BF16 = 0x4
+ROW_MAJOR = 0x00
+COL_MAJOR = 0x10
+LEAF_F64 = 0x20
+GP_MFMA_BF16 = 0x100
+GP_SIMD_F32 = 0x200
+MAX_N = 128
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+
+class TsqrConfig(ctypes.Structure):
+    _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32)]
+
+
+class MatrixDesc(ctypes.Structure):
+    _fields_ = [("X", _vp), ("m", _i64), ("n", _i64), ("ld", _i64), ("R", _vp), ("colsum", _vp)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_tsqr_r = _sig("tsnmf_tsqr_r", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
+_tsqr_r_ex = _sig("tsnmf_tsqr_r_ex", ctypes.c_int,
+                  [_vp, _i64, _i64, _i64, _u32, _vp, _vp, ctypes.POINTER(TsqrConfig), _vp])
+_plan_create = _sig("tsnmf_batch_plan_create", ctypes.c_int,
+                    [_i32, ctypes.POINTER(MatrixDesc), _u32, ctypes.POINTER(_vp)])
+_tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_vp, _vp])
+_plan_destroy = _sig("tsnmf_batch_plan_destroy", ctypes.c_int, [_vp])
+_gauss_proj = _sig("tsnmf_gauss_proj", ctypes.c_int,
+                   [_vp, _i64, _i64, _i64, _u32, _i32, _u64, _i64, _vp, _vp, _vp])
+_select_spa = _sig("tsnmf_select_spa", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp])
+_select_xray = _sig("tsnmf_select_xray", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp])
+_select_gp = _sig("tsnmf_select_gp", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp])
+_nnls = _sig("tsnmf_nnls", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp])
+_residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
+_reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
+_status_string = _sig("tsnmf_status_string", ctypes.c_char_p, [ctypes.c_int])
+_last_hip_error = _sig("tsnmf_last_hip_error", ctypes.c_int, [])
+_version = _sig("tsnmf_version", ctypes.c_int, [])
+
+
+class TsnmfError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = _status_string(status).decode()
+        if status == 1:
+            msg += f" (hip error {_last_hip_error()})"
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(fn, st):
+    if st != 0:
+        raise TsnmfError(fn, st)
+    return st
+
+
+# ---- same-name entry points (marshalling only) ---------------------------------------
+
+def tsnmf_tsqr_r(X, m, n, ld, flags, R, colsum=None, stream=None):
+    return _tsqr_r(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), _stream(stream))
+
+
+def tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):
+    c = None if cfg is None else ctypes.byref(cfg)
+    return _tsqr_r_ex(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), c, _stream(stream))
+
+
+def tsnmf_batch_plan_create(descs, flags):
+    arr = (MatrixDesc * len(descs))(*descs)
+    h = _vp()
+    st = _plan_create(len(descs), arr, flags, ctypes.byref(h))
+    return st, h
+
+
+def tsnmf_tsqr_r_batched(plan, stream=None):
+    return _tsqr_batched(plan, _stream(stream))
+
+
+def tsnmf_batch_plan_destroy(plan):
+    return _plan_destroy(plan)
+
+
+def tsnmf_gauss_proj(X, m, n, ld, flags, k, seed, row_offset, Y, colsum=None, stream=None):
+    return _gauss_proj(_ptr(X), m, n, ld, flags, k, seed, row_offset, _ptr(Y), _ptr(colsum), _stream(stream))
+
+
+def tsnmf_select_spa(M, p, n, ldm, colscale, r, K, score, info, stream=None):
+    return _select_spa(_ptr(M), p, n, ldm, _ptr(colscale), r, _ptr(K), _ptr(score), _ptr(info), _stream(stream))
+
+
+def tsnmf_select_xray(M, p, n, ldm, r, K, info, stream=None):
+    return _select_xray(_ptr(M), p, n, ldm, r, _ptr(K), _ptr(info), _stream(stream))
+
+
+def tsnmf_select_gp(Y, k, n, ldy, colscale, r, K, counts, info, stream=None):
+    return _select_gp(_ptr(Y), k, n, ldy, _ptr(colscale), r, _ptr(K), _ptr(counts), _ptr(info), _stream(stream))
+
+
+def tsnmf_nnls(M, p, n, ldm, K, r, H, ldh, resid2=None, info=None, stream=None):
+    return _nnls(_ptr(M), p, n, ldm, _ptr(K), r, _ptr(H), ldh, _ptr(resid2), _ptr(info), _stream(stream))
+
+
+def tsnmf_residual(M, p, n, ldm, K, r, H, ldh, relerr, stream=None):
+    return _residual(_ptr(M), p, n, ldm, _ptr(K), r, _ptr(H), ldh, _ptr(relerr), _stream(stream))
+
+
+def tsnmf_reserve(max_m, max_n, max_k=0):
+    return _reserve(max_m, max_n, max_k)
+
+
+def tsnmf_status_string(status):
+    return _status_string(status).decode()
+
+
+def tsnmf_last_hip_error():
+    return _last_hip_error()
+
+
+def tsnmf_version():
+    return _version()
+
+
+# ---- convenience wrappers (allocate outputs with torch) --------------------------------
+
+def _layout(X):
+    """(flags, ld) for a 2-D CUDA tensor that is row-major or column-major."""
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D")
+    m, n = X.shape
+    if X.stride(1) == 1 and (X.stride(0) >= n or m == 1):
+        return ROW_MAJOR, max(X.stride(0), n)
+    if X.stride(0) == 1 and (X.stride(1) >= m or n == 1):
+        return COL_MAJOR, max(X.stride(1), m)
+    raise ValueError("X must be row-major or column-major with unit inner stride")
+
+
+_DTYPE_FLAG = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+def colmajor_square(buf):
+    """Logical view of a column-major square output buffer."""
+    return buf.t()
+
+
+def tsqr_r(X, leaf_f64=False, config=None, stream=None, with_colsum=True):
+    """R (n x n, FP64, diag >= 0) and the l1 column sums of a CUDA tensor X."""
+    m, n = X.shape
+    lay, ld = _layout(X)
+    flags = _DTYPE_FLAG[X.dtype] | lay | (LEAF_F64 if leaf_f64 else 0)
+    Rbuf = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    cs = torch.empty(n, dtype=torch.float64, device=X.device) if with_colsum else None
+    if config is None:
+        st = tsnmf_tsqr_r(X, m, n, ld, flags, Rbuf, cs, stream)
+    else:
+        st = tsnmf_tsqr_r_ex(X, m, n, ld, flags, Rbuf, cs, config, stream)
+    _check("tsnmf_tsqr_r", st)
+    return colmajor_square(Rbuf), cs
+
+
+def gauss_proj(X, k, seed, mode=None, row_offset=0, stream=None, with_colsum=False):
+    """Y = G^T X (k x n, FP32) with the library's Philox-defined G."""
+    m, n = X.shape
+    lay, ld = _layout(X)
+    if lay != ROW_MAJOR:
+        raise ValueError("gauss_proj expects a row-major X")
+    if mode is None:
+        mode = GP_MFMA_BF16 if X.dtype == torch.bfloat16 else GP_SIMD_F32
+    flags = _DTYPE_FLAG[X.dtype] | mode
+    Ybuf = torch.empty((n, k), dtype=torch.float32, device=X.device)   # column-major k x n
+    cs = torch.empty(n, dtype=torch.float64, device=X.device) if with_colsum else None
+    _check("tsnmf_gauss_proj", tsnmf_gauss_proj(X, m, n, ld, flags, k, seed, row_offset, Ybuf, cs, stream))
+    return Ybuf.t(), cs
+
+
+def _colmajor_input(M):
+    """(buffer, ld) of a logical matrix for the column-major small solvers."""
+    if M.stride(0) == 1 and M.stride(1) >= M.shape[0]:
+        return M, M.stride(1)
+    buf = M.t().contiguous()          # column-major copy
+    return buf.t(), M.shape[0]
+
+
+def select_spa(M, r, colscale=None, stream=None):
+    p, n = M.shape
+    Mc, ldm = _colmajor_input(M)
+    K = torch.empty(r, dtype=torch.int32, device=M.device)
+    score = torch.empty(r, dtype=torch.float64, device=M.device)
+    info = torch.empty(1, dtype=torch.int32, device=M.device)
+    _check("tsnmf_select_spa", tsnmf_select_spa(Mc, p, n, ldm, colscale, r, K, score, info, stream))
+    return K, score, info
+
+
+def select_xray(M, r, stream=None):
+    p, n = M.shape
+    Mc, ldm = _colmajor_input(M)
+    K = torch.empty(r, dtype=torch.int32, device=M.device)
+    info = torch.empty(1, dtype=torch.int32, device=M.device)
+    _check("tsnmf_select_xray", tsnmf_select_xray(Mc, p, n, ldm, r, K, info, stream))
+    return K, info
+
+
+def select_gp(Y, r, colscale=None, stream=None):
+    k, n = Y.shape
+    Yc, ldy = _colmajor_input(Y)
+    K = torch.empty(r, dtype=torch.int32, device=Y.device)
+    counts = torch.empty(n, dtype=torch.int32, device=Y.device)
+    info = torch.empty(1, dtype=torch.int32, device=Y.device)
+    _check("tsnmf_select_gp", tsnmf_select_gp(Yc, k, n, ldy, colscale, r, K, counts, info, stream))
+    return K, counts, info
+
+
+def nnls(M, K, stream=None):
+    p, n = M.shape
+    r = K.numel()
+    Mc, ldm = _colmajor_input(M)
+    Hbuf = torch.empty((n, r), dtype=torch.float64, device=M.device)   # column-major r x n
+    res = torch.empty(n, dtype=torch.float64, device=M.device)
+    info = torch.empty(n, dtype=torch.int32, device=M.device)
+    _check("tsnmf_nnls", tsnmf_nnls(Mc, p, n, ldm, K, r, Hbuf, r, res, info, stream))
+    return Hbuf.t(), res, info
+
+
+def residual(M, K, H, stream=None):
+    p, n = M.shape
+    r = K.numel()
+    Mc, ldm = _colmajor_input(M)
+    Hc, ldh = _colmajor_input(H)
+    out = torch.empty(1, dtype=torch.float64, device=M.device)
+    _check("tsnmf_residual", tsnmf_residual(Mc, p, n, ldm, K, r, Hc, ldh, out, stream))
+    return out
+
+
+def reserve(max_m, max_n, max_k=0):
+    _check("tsnmf_reserve", tsnmf_reserve(max_m, max_n, max_k))

@@ -85,10 +85,11 @@ extern "C" {
  *   colsum  device FP64[n] or NULL; output colsum[j] = sum_i |X(i, j)|.
  *
  * Row blocks are factored by Householder reflections in the input precision
- * (FP32 for F32 input unless TSNMF_LEAF_F64), each workgroup keeping a running
- * R for its contiguous slab of rows; the slab factors are combined by a tree
- * of FP64 QR factorisations of stacked triangles.  The result is
- * deterministic for a given (m, n, flags, configuration).
+ * (FP32 for F32 input unless TSNMF_LEAF_F64), each wave keeping a running R
+ * for its contiguous slab of rows (the leaf); the leaf factors are combined by
+ * a binary tree of FP64 QR factorisations of stacked triangles, all in one
+ * kernel launch.  The result is deterministic for a given (m, n, flags,
+ * configuration).
  */
 int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
                  double* R, double* colsum, hipStream_t stream);
@@ -97,7 +98,7 @@ int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags
 typedef struct tsnmf_tsqr_config {
     int64_t leaf_rows;      /* rows per workgroup slab (the TSQR leaf); rounded up
                                to a whole number of row blocks                    */
-    int32_t tree_arity;     /* slab factors merged per tree node, 2..64          */
+    int32_t tree_arity;     /* slab factors merged per tree node: 0 or 2 (binary) */
     int32_t rows_per_lane;  /* row block height = 64 * rows_per_lane; 1..8        */
 } tsnmf_tsqr_config;
 
@@ -239,6 +240,15 @@ int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int
    n <= max_n, and projections with k <= max_k, need no allocation (required
    before graph capture).  Host call, synchronous. */
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
+
+/* Profiling aid.  While enabled (on != 0), TSQR and projection calls record
+   HIP events on their stream around their main kernel ("stage 0": the leaf /
+   projection kernel) and around the rest of the call ("stage 1": reduction
+   tree and finalisation).  tsnmf_profile_query waits for the recorded events
+   (host synchronisation), returns the summed elapsed milliseconds and the
+   number of calls of a stage, and clears that stage.  Not for graph capture. */
+int tsnmf_profile_enable(int on);
+int tsnmf_profile_query(int stage, double* total_ms, int64_t* calls);
 
 /* Human-readable text of a return code (static storage). */
 const char* tsnmf_status_string(int status);

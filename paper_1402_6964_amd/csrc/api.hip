@@ -40,11 +40,36 @@ int grow(int dev, size_t bytes) {
         (void)hipGetLastError();
         return TSNMF_ERR_NOMEM;
     }
+    e = hipMemset(p, 0, kTicketBytes);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e);
+    }
     w.ptr = p;
     w.bytes = sz;
     return TSNMF_OK;
 }
+struct ProfileStage {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+ProfileStage g_prof[2];
 }  // namespace
+
+bool profiling_on() { return g_prof_on; }
+
+int profile_event(hipStream_t s, hipEvent_t* ev) {
+    TSNMF_HIP(hipEventCreate(ev));
+    TSNMF_HIP(hipEventRecord(*ev, s));
+    return TSNMF_OK;
+}
+
+int profile_record(int stage, hipEvent_t start, hipEvent_t stop) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[stage].pending.emplace_back(start, stop);
+    return TSNMF_OK;
+}
 
 int hip_fail(hipError_t e) {
     g_last_hip = (int)e;
@@ -91,7 +116,7 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
         return -5;
     if (R == nullptr) return -6;
     if (cfg != nullptr) {
-        if (cfg->leaf_rows < 0 || cfg->tree_arity < 0 || cfg->tree_arity == 1 || cfg->tree_arity > 64 ||
+        if (cfg->leaf_rows < 0 || (cfg->tree_arity != 0 && cfg->tree_arity != 2) ||
             cfg->rows_per_lane < 0 || cfg->rows_per_lane > 8)
             return -8;
     }
@@ -112,6 +137,35 @@ int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
     size_t b = 0;
     if (max_m > 0 && max_n > 0) b = tsqr_workspace_bytes(max_m, max_n);
     return workspace_reserve(b);
+}
+
+int tsnmf_profile_enable(int on) {
+    g_prof_on = on != 0;
+    return TSNMF_OK;
+}
+
+int tsnmf_profile_query(int stage, double* total_ms, int64_t* calls) {
+    if (stage < 0 || stage > 1) return -1;
+    if (total_ms == nullptr) return -2;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        ev.swap(g_prof[stage].pending);
+    }
+    double sum = 0.0;
+    int st = TSNMF_OK;
+    for (auto& pr : ev) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess && st == TSNMF_OK) st = hip_fail(e);
+        sum += ms;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    *total_ms = sum;
+    if (calls != nullptr) *calls = (int64_t)ev.size();
+    return st;
 }
 
 const char* tsnmf_status_string(int status) {

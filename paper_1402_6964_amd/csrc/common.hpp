@@ -19,6 +19,12 @@ int hip_fail(hipError_t e);
 
 #define TSNMF_LAUNCH_CHECK() TSNMF_HIP(hipGetLastError())
 
+// The first kTicketBytes of every device workspace hold the reduction-tree
+// tickets; they are zeroed when the workspace is allocated and every call
+// leaves them zero again.
+constexpr size_t kTicketBytes = 64 * 1024;
+constexpr int64_t kMaxLeaves = (int64_t)(kTicketBytes / sizeof(int));
+
 // Grow-only per-device workspace.  `bytes` is the size needed; returns a
 // device pointer aligned to 256 bytes or a status (TSNMF_ERR_CAPTURE when the
 // stream is capturing and the workspace is too small, TSNMF_ERR_NOMEM).
@@ -28,6 +34,12 @@ int workspace_reserve(size_t bytes);
 // Bytes of workspace one TSQR call of this shape needs (for tsnmf_reserve).
 size_t tsqr_workspace_bytes(int64_t m, int n);
 size_t gp_workspace_bytes(int64_t m, int n, int k);
+
+// Profiling (see tsnmf_profile_enable): profile_event creates and records an
+// event on the stream; profile_record files a (start, stop) pair under a stage.
+bool profiling_on();
+int profile_record(int stage, hipEvent_t start, hipEvent_t stop);
+int profile_event(hipStream_t s, hipEvent_t* ev);
 
 // Implementations behind the C entry points (arguments already validated).
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,

@@ -17,37 +17,22 @@
 // The block's l1 column sums (Sec. 3.3) are reduced by one more butterfly and
 // accumulated in FP64.
 //
-// The same kernel, instantiated in FP64, combines the slab factors: the
-// stacked n x n partial R's of `group` slabs are just a taller input.
+// The slab factors are then combined by the FP64 tree of tsqr_tree.hpp.
 #pragma once
+#include "tsqr_tree.hpp"
 #include "wave.hpp"
 
 namespace tsnmf {
 
 enum LoadKind : int { LOAD_ROW = 0, LOAD_ROW_STAGED = 1, LOAD_COL = 2 };
-enum CsMode : int { CS_NONE = 0, CS_DATA = 1, CS_PARTIALS = 2 };
-
 struct StreamArgs {
     const void* X;         // input of element type TI, rows [0, m)
     int64_t m;             // rows
     int64_t ld;            // leading dimension (elements)
     int64_t slab;          // rows per stream
-    int64_t nstreams;      // streams (one wave each)
-    int32_t load;          // LoadKind
-    int32_t cs_mode;       // CsMode
-    const double* in_cs;   // CS_PARTIALS: [nin][n] partial column sums
-    int64_t nin;           // CS_PARTIALS: number of input partials
-    int32_t group;         // CS_PARTIALS: partials summed per stream
-    int32_t pad_;
-    double* out_R;         // [nstreams][n][n] row-major, zeros below diagonal
-    double* out_cs;        // [nstreams][n] (CS_DATA / CS_PARTIALS)
+    int64_t nstreams;      // streams (one wave each) = tree leaves
+    TreeArgs tree;         // reduction tree and final outputs
 };
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename T> __device__ __forceinline__ T rcp_fast(T x);
 template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -73,12 +58,18 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     static constexpr int SS = (N % 2) ? N : N + 1;        // staging row stride, odd -> no bank conflicts
     static constexpr int STG = 64 * SS;                   // staging elements (TI) per wave
     static constexpr size_t r_bytes() { return (size_t)4 * RS * sizeof(T); }
+    static constexpr size_t stage_off() { return (r_bytes() + 15) & ~(size_t)15; }
     static constexpr size_t lds_bytes(bool staged) {  // per workgroup of 4 waves
-        return ((r_bytes() + 15) & ~(size_t)15) + (staged ? (size_t)4 * STG * sizeof(TI) : 0);
+        return stage_off() + (staged ? (size_t)4 * STG * sizeof(TI) : 0);
     }
 
     // ---- one Householder step (column J) -------------------------------------
-    template <int J> static __device__ __forceinline__ void step(T (&x)[RPL][N], T* Rl) {
+    // With `xchg` non-null, W waves of a workgroup hold different rows of the
+    // same block: after its butterfly each wave publishes its 64 lane values,
+    // and every wave adds all W of them in wave order (the same sums in every
+    // wave, so the W copies of R stay identical).
+    template <int J, int W = 1>
+    static __device__ __forceinline__ void step(T (&x)[RPL][N], T* Rl, T* xchg = nullptr) {
         if constexpr (J < N) {
             constexpr int CNT = N - J;
             constexpr int V = pow2ceil(CNT);
@@ -96,7 +87,16 @@ template <typename T, typename TI, int N, int RPL> struct Small {
                     p[v] = T(0);
                 }
             }
-            const T D = butterfly<P>(p);             // lane L: d_{J + vidx(L)}
+            T D = butterfly<P>(p);                   // lane L: d_{J + vidx(L)}
+            if constexpr (W > 1) {
+                const int wv = (int)(threadIdx.x >> 6);
+                T* xb = xchg + (J & 1) * (W * 64);   // alternate buffers: one barrier per step
+                xb[wv * 64 + L] = D;
+                __syncthreads();
+                D = xb[L];
+#pragma unroll
+                for (int q = 1; q < W; ++q) D += xb[q * 64 + L];
+            }
             const int vi = bfly_vidx<P>(L);
             T* row = Rl + roff(J);
             const T rj = row[vi];                    // R(J, J + vi), zero in padding slots
@@ -122,7 +122,7 @@ template <typename T, typename TI, int N, int RPL> struct Small {
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
             }
-            step<J + 1>(x, Rl);
+            step<J + 1, W>(x, Rl, xchg);
         }
     }
 
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
     const int64_t sid = (int64_t)blockIdx.x * 4 + wv;
     if (sid >= a.nstreams) return;                      // whole wave; no block barriers used
     T* Rl = (T*)smem + wv * S::RS;
-    TI* St = (TI*)(smem + ((S::r_bytes() + 15) & ~(size_t)15)) + wv * S::STG;
+    TI* St = (TI*)(smem + S::stage_off()) + wv * S::STG;
 
     for (int i = L; i < S::RS; i += 64) Rl[i] = T(0);
     wave_lds_sync();
@@ -219,32 +219,132 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
     for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
         T x[RPL][N];
         S::template load<LOAD>(x, a, b0, r1, St);
-        if (a.cs_mode == CS_DATA) S::colsum_block(x, acc);
+        S::colsum_block(x, acc);
         S::template step<0>(x, Rl);
     }
     wave_lds_sync();
 
-    // Partial R, row-major with explicit zeros below the diagonal.
-    double* out = a.out_R + sid * (int64_t)N * N;
+    // Leaf node of the tree: R in FP64, row-major with zeros below the diagonal.
+    double* out = a.tree.nodes + sid * (int64_t)N * N;
     int off = 0;
     for (int j = 0; j < N; ++j) {
         if (L < N) out[j * N + L] = L >= j ? (double)Rl[off + (L - j)] : 0.0;
         off += pow2ceil(N - j);
     }
-    if (a.cs_mode == CS_DATA) {
-        int src = 0;                                    // lane holding column L's sum
-        for (int s2 = 0; s2 < S::PN; ++s2) src |= ((L >> s2) & 1) << (5 - s2);
-        const double v = lane_gather(acc, src);
-        if (L < N) a.out_cs[sid * N + L] = v;
-    } else if (a.cs_mode == CS_PARTIALS) {
-        if (L < N) {
-            double s = 0.0;
-            for (int t = 0; t < a.group; ++t) {
-                const int64_t idx = sid * a.group + t;
-                if (idx < a.nin) s += a.in_cs[idx * N + L];
-            }
-            a.out_cs[sid * N + L] = s;
+    int src = 0;                                        // lane holding column L's sum
+    for (int s2 = 0; s2 < S::PN; ++s2) src |= ((L >> s2) & 1) << (5 - s2);
+    const double v = lane_gather(acc, src);
+    if (L < N) a.tree.node_cs[sid * N + L] = v;
+}
+
+// ---- FP64 reduction tree over the slab factors ---------------------------------
+//
+// One pass of a workgroup (8 waves) reduces a group of G consecutive nodes of
+// the current tree level to one node: the G stacked n x n triangles are rows of
+// a single block of 8 x 128 rows, factored by the same structured Householder
+// steps in FP64 with the waves' partial sums added through LDS in wave order
+// (Sec. 3.5: the reduce stage factors the stacked R factors).  The node goes to
+// the next level; by ticket, the last workgroup of each group of G continues
+// with that group, so all levels run in one launch.  The pass that finds a
+// single node at the next level writes the final R (column-major, rows
+// flipped to a nonnegative diagonal) and the column sums.  Groups and orders
+// are fixed, so the result is deterministic.
+template <int N> struct CoopTree {
+    static constexpr int W = 8;                       // waves per workgroup
+    static constexpr int RPL = 2;                     // FP64 rows per lane
+    static constexpr int CAP = W * 64 * RPL;          // rows per pass
+    static constexpr int G = CAP / N < 64 ? CAP / N : 64;   // nodes per pass
+};
+
+template <int N> constexpr int64_t coop_tree_nodes(int64_t leaves) {
+    int64_t total = 0, c = leaves;
+    while (c > 1) {
+        total += c;
+        c = (c + CoopTree<N>::G - 1) / CoopTree<N>::G;
+    }
+    return total + 1;
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) tsqr_coop_tree_kernel(TreeArgs t) {
+    using CT = CoopTree<N>;
+    using S = Small<double, double, N, CT::RPL>;
+    constexpr int G = CT::G;
+    constexpr int64_t NN = (int64_t)N * N;
+    __shared__ double sR[CT::W][S::RS];
+    __shared__ double xchg[2 * CT::W * 64];
+    __shared__ int go;
+    const int wv = (int)(threadIdx.x >> 6);
+    const int L = lane_id();
+    double* Rl = sR[wv];
+
+    int64_t group = blockIdx.x;   // group index within the current level
+    int64_t count = t.leaves;     // nodes at the current level
+    int64_t base = 0;             // node offset of the current level
+    int64_t tbase = 0;            // ticket offset of the next level
+    while (true) {
+        const int64_t first = group * G;
+        const int rows = (int)min((int64_t)G, count - first) * N;
+        for (int i = L; i < S::RS; i += 64) Rl[i] = 0.0;
+        wave_lds_sync();
+        double x[CT::RPL][N];
+        const double* src = t.nodes + (base + first) * NN;    // stacked rows, n wide
+#pragma unroll
+        for (int r = 0; r < CT::RPL; ++r) {
+            const int b = wv * (64 * CT::RPL) + r * 64 + L;
+            const bool ok = b < rows;
+            const double* rowp = src + (int64_t)min(b, rows - 1) * N;
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[r][c] = ok ? rowp[c] : 0.0;
         }
+        S::template step<0, CT::W>(x, Rl, xchg);
+        wave_lds_sync();
+        double cs = 0.0;
+        if (wv == 0 && L < N) {
+            const int cnt = rows / N;
+            for (int q = 0; q < cnt; ++q) cs += t.node_cs[(base + first + q) * N + L];
+        }
+        const int64_t ncount = (count + G - 1) / G;
+        if (ncount == 1) {                                   // root
+            if (wv == 0) {
+                int off = 0;
+                for (int j = 0; j < N; ++j) {
+                    const double djj = Rl[off];
+                    if (L < N) t.R[(int64_t)L * N + j] = L >= j ? (djj < 0.0 ? -Rl[off + L - j] : Rl[off + L - j]) : 0.0;
+                    off += pow2ceil(N - j);
+                }
+                if (t.colsum != nullptr && L < N) t.colsum[L] = cs;
+            }
+            return;
+        }
+        const int64_t nbase = base + count;
+        if (wv == 0) {
+            double* out = t.nodes + (nbase + group) * NN;
+            int off = 0;
+            for (int j = 0; j < N; ++j) {
+                if (L < N) out[j * N + L] = L >= j ? Rl[off + (L - j)] : 0.0;
+                off += pow2ceil(N - j);
+            }
+            if (L < N) t.node_cs[(nbase + group) * N + L] = cs;
+        }
+        __syncthreads();
+        const int64_t ngroup = group / G;
+        const int gsize = (int)min((int64_t)G, ncount - ngroup * G);
+        if (threadIdx.x == 0) {
+            grid_release();
+            const int old = __hip_atomic_fetch_add(t.tickets + tbase + ngroup, 1, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            const int last = old == gsize - 1;
+            if (last) __hip_atomic_store(t.tickets + tbase + ngroup, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            go = last;
+        }
+        __syncthreads();
+        if (!go) return;
+        grid_acquire();
+        tbase += (ncount + G - 1) / G;
+        base = nbase;
+        count = ncount;
+        group = ngroup;
     }
 }
 

@@ -29,6 +29,13 @@ hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
     }
     const unsigned grid = (unsigned)((a.nstreams + 3) / 4);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // reduction tree: one workgroup per group of G leaves, later levels by ticket
+    constexpr int G = CoopTree<N>::G;
+    const int64_t groups = (a.tree.leaves + G - 1) / G;
+    hipLaunchKernelGGL(tsqr_coop_tree_kernel<N>, dim3((unsigned)groups), dim3(CoopTree<N>::W * 64), 0, stream,
+                       a.tree);
     return hipGetLastError();
 }
 

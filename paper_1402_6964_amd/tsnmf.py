@@ -68,6 +68,9 @@ _select_gp = _sig("tsnmf_select_gp", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, 
 _nnls = _sig("tsnmf_nnls", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp])
 _residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
 _reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
+_profile_enable = _sig("tsnmf_profile_enable", ctypes.c_int, [ctypes.c_int])
+_profile_query = _sig("tsnmf_profile_query", ctypes.c_int,
+                      [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
 _status_string = _sig("tsnmf_status_string", ctypes.c_char_p, [ctypes.c_int])
 _last_hip_error = _sig("tsnmf_last_hip_error", ctypes.c_int, [])
 _version = _sig("tsnmf_version", ctypes.c_int, [])
@@ -156,6 +159,18 @@ def tsnmf_residual(M, p, n, ldm, K, r, H, ldh, relerr, stream=None):
 
 def tsnmf_reserve(max_m, max_n, max_k=0):
     return _reserve(max_m, max_n, max_k)
+
+
+def tsnmf_profile_enable(on):
+    return _profile_enable(1 if on else 0)
+
+
+def tsnmf_profile_query(stage):
+    """(status, total_ms, calls) of a profiling stage; clears it."""
+    ms = ctypes.c_double()
+    n = _i64()
+    st = _profile_query(stage, ctypes.byref(ms), ctypes.byref(n))
+    return st, ms.value, n.value
 
 
 def tsnmf_status_string(status):

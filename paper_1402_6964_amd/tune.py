@@ -1,0 +1,110 @@
+"""Autotuner for the TSQR launch geometry (leaf height and row block size).
+
+    python -m paper_1402_6964_amd.tune --m 10000000 --n 25 [--dtype f32] [--layout row]
+
+For one input shape it times tsnmf_tsqr_r_ex over a grid of leaf heights
+(rows per slab) with HIP events, rejects any configuration whose R differs
+from the default configuration's by more than the rounding bound of the
+precision used (every configuration computes the same R up to rounding), and
+records the fastest in paper_1402_6964_amd/tuned.json, keyed by
+(dtype, layout, n, floor(log2 m)).  The Python binding's tsqr_r() looks the
+key up when no explicit configuration is given.
+"""
+
+import argparse
+import json
+import math
+import os
+
+import torch
+
+from . import synth, tsnmf
+
+TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def key(dtype, layout, n, m):
+    return f"{dtype}:{layout}:{n}:{int(math.log2(max(m, 1)))}"
+
+
+def load():
+    try:
+        with open(TUNED) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(dtype, layout, n, m):
+    e = load().get(key(dtype, layout, n, m))
+    if e is None:
+        return None
+    return tsnmf.TsqrConfig(leaf_rows=int(e["leaf_rows"]), tree_arity=0, rows_per_lane=0)
+
+
+def time_config(X, cfg, reps=20):
+    m, n = X.shape
+    lay, ld = tsnmf._layout(X)
+    flags = tsnmf._DTYPE_FLAG[X.dtype] | lay
+    Rbuf = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    cs = torch.empty(n, dtype=torch.float64, device=X.device)
+    for _ in range(3):
+        tsnmf._check("tsnmf_tsqr_r_ex", tsnmf.tsnmf_tsqr_r_ex(X, m, n, ld, flags, Rbuf, cs, cfg))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        tsnmf.tsnmf_tsqr_r_ex(X, m, n, ld, flags, Rbuf, cs, cfg)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps, Rbuf.t().cpu()
+
+
+def tune(X, leaf_grid=None, verbose=True):
+    m, n = X.shape
+    lay, _ = tsnmf._layout(X)
+    t0, R0 = time_config(X, None)
+    tol = 1e-5 if X.dtype == torch.float32 else 1e-11
+    if leaf_grid is None:
+        leaf_grid = sorted({max(64, m // p) for p in (64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096)})
+    best = (t0, 0)
+    results = [{"leaf_rows": 0, "ms": t0}]
+    for leaf in leaf_grid:
+        cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=0, rows_per_lane=0)
+        ms, R = time_config(X, cfg)
+        err = float((R - R0).abs().max() / R0.abs().max())
+        ok = err <= tol
+        results.append({"leaf_rows": int(leaf), "ms": ms, "err": err, "ok": ok})
+        if verbose:
+            print(f"leaf_rows {leaf:9d}  {ms:8.3f} ms  {m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}",
+                  flush=True)
+        if ok and ms < best[0]:
+            best = (ms, int(leaf))
+    dt = {torch.float32: "f32", torch.float64: "f64"}[X.dtype]
+    lname = "col" if lay == tsnmf.COL_MAJOR else "row"
+    return key(dt, lname, n, m), {"leaf_rows": best[1], "ms": best[0], "default_ms": t0}, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--m", type=int, default=10_000_000)
+    ap.add_argument("--n", type=int, default=25)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--layout", choices=["row", "col"], default="row")
+    ap.add_argument("--no-save", action="store_true")
+    args = ap.parse_args()
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+    if args.layout == "row":
+        X = synth.random_matrix(args.m, args.n, device="cuda", dtype=dt, seed_tag=11)
+    else:
+        X = synth.random_matrix(args.n, args.m, device="cuda", dtype=dt, seed_tag=11).t()
+    k, best, _ = tune(X)
+    print(json.dumps({k: best}))
+    if not args.no_save:
+        table = load()
+        table[k] = best
+        with open(TUNED, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,7 +120,7 @@ def test_configs_give_the_same_r(lib):
     """Tree invariance on the GPU: leaf heights / arities change only rounding."""
     X = synth.random_matrix(123_457, 12, dtype=torch.float32, seed_tag=6).cuda()
     R0, _ = _run(lib, X)
-    for leaf, arity in [(256, 2), (1000, 3), (5000, 64), (123_457, 2)]:
+    for leaf, arity in [(256, 2), (1000, 0), (5000, 2), (64, 2), (123_457, 2)]:
         cfg = lib.TsqrConfig(leaf_rows=leaf, tree_arity=arity, rows_per_lane=0)
         R1, _ = _run(lib, X, config=cfg)
         assert np.abs(R1 - R0).max() / np.abs(R0).max() <= 1e-5
@@ -188,3 +188,5 @@ def test_invalid_arguments(lib):
     assert lib.tsnmf_tsqr_r(X, 10, 4, 4, lib.BF16, R) == -5
     assert lib.tsnmf_tsqr_r(X, 10, 4, 4, lib.F32, None) == -6
     assert lib.tsnmf_tsqr_r(X, 10, 300, 300, lib.F32, R) == 4
+    bad = lib.TsqrConfig(leaf_rows=0, tree_arity=3, rows_per_lane=0)
+    assert lib.tsnmf_tsqr_r_ex(X, 10, 4, 4, lib.F32, R, None, bad) == -8

@@ -121,7 +121,6 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
             return -8;
     }
     if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
-    if (n > 32) return TSNMF_ERR_UNSUPPORTED;
     return tsqr_r_impl(X, m, (int)n, ld, flags, R, colsum, cfg, stream);
 }
 

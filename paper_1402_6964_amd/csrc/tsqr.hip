@@ -3,7 +3,7 @@
 #include <algorithm>
 
 #include "common.hpp"
-#include "tsqr_small.hpp"
+#include "tsqr_wide.hpp"
 
 namespace tsnmf {
 
@@ -15,6 +15,12 @@ hipError_t launch_small_f64_row(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f64_col(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f32w_row(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f32w_col(int n, const StreamArgs& a, hipStream_t s);
+hipError_t launch_wide_f32_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f64_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f64_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32w_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32w_col(const WideArgs& a, hipStream_t s);
 int rows_per_lane_f32(int n);
 int rows_per_lane_f64(int n);
 
@@ -40,8 +46,20 @@ hipError_t launch_leaf(Path p, int load, int n, const StreamArgs& a, hipStream_t
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
+    const bool col = load == LOAD_COL;
+    switch (p) {
+        case Path::F32: return col ? launch_wide_f32_col(a, s) : launch_wide_f32_row(a, s);
+        case Path::F64: return col ? launch_wide_f64_col(a, s) : launch_wide_f64_row(a, s);
+        case Path::F32W: return col ? launch_wide_f32w_col(a, s) : launch_wide_f32w_row(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 struct Plan {
     Path path;
+    bool wide;
+    int waves;       // waves per slab
     int load;
     int64_t block_rows;
     int64_t slab;
@@ -54,16 +72,19 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     const bool col = (flags & TSNMF_COL_MAJOR) != 0;
     if (dt == TSNMF_F64) p.path = Path::F64;
     else p.path = (flags & TSNMF_LEAF_F64) ? Path::F32W : Path::F32;
+    p.wide = n > 32;
+    p.waves = !p.wide ? 1 : (n <= 64 ? 2 : 4);
     if (col) p.load = LOAD_COL;
-    else if (ld == n && p.path != Path::F32W) p.load = LOAD_ROW_STAGED;
+    else if (ld == n && p.path != Path::F32W && !p.wide) p.load = LOAD_ROW_STAGED;
     else p.load = LOAD_ROW;
-    const int rpl = p.path == Path::F32 ? rows_per_lane_f32(n) : rows_per_lane_f64(n);
+    const int rpl = p.wide ? (p.path == Path::F32 ? 4 : 2)
+                           : (p.path == Path::F32 ? rows_per_lane_f32(n) : rows_per_lane_f64(n));
     p.block_rows = 64LL * rpl;
     if (cfg != nullptr && cfg->leaf_rows > 0) {
         p.slab = cfg->leaf_rows;
     } else {
         const int64_t blocks = (m + p.block_rows - 1) / p.block_rows;
-        const int64_t streams = std::max<int64_t>(1, std::min<int64_t>(blocks, kTargetStreams));
+        const int64_t streams = std::max<int64_t>(1, std::min<int64_t>(blocks, kTargetStreams / p.waves));
         p.slab = ((blocks + streams - 1) / streams) * p.block_rows;
     }
     // the ticket area bounds the number of leaves
@@ -103,24 +124,38 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
     if (int st = workspace_get(plan_bytes(p, n), stream, &ws)) return st;
     const int64_t nodes = tree_nodes(p.streams);
     char* base = (char*)ws;
+    TreeArgs tree{};
+    tree.tickets = (int*)base;
+    tree.nodes = (double*)(base + kTicketBytes);
+    tree.node_cs = (double*)(base + kTicketBytes + align256(nodes * (size_t)n * n * 8));
+    tree.leaves = p.streams;
+    tree.R = R;
+    tree.colsum = colsum;
     StreamArgs a{};
     a.X = X;
     a.m = m;
     a.ld = ld;
     a.slab = p.slab;
     a.nstreams = p.streams;
-    a.tree.tickets = (int*)base;
-    a.tree.nodes = (double*)(base + kTicketBytes);
-    a.tree.node_cs = (double*)(base + kTicketBytes + align256(nodes * (size_t)n * n * 8));
-    a.tree.leaves = p.streams;
-    a.tree.R = R;
-    a.tree.colsum = colsum;
+    a.tree = tree;
+    WideArgs aw{};
+    aw.X = X;
+    aw.m = m;
+    aw.ld = ld;
+    aw.slab = p.slab;
+    aw.nstreams = p.streams;
+    aw.n = n;
+    aw.tree = tree;
     const bool prof = profiling_on();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
         if (int st = profile_event(stream, &e0)) return st;
     }
-    TSNMF_HIP(launch_leaf(p.path, p.load, n, a, stream));
+    if (p.wide) {
+        TSNMF_HIP(launch_wide(p.path, p.load, aw, stream));
+    } else {
+        TSNMF_HIP(launch_leaf(p.path, p.load, n, a, stream));
+    }
     if (prof) {
         if (int st = profile_event(stream, &e1)) return st;
         profile_record(0, e0, e1);

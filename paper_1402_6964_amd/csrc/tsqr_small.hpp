@@ -34,9 +34,17 @@ struct StreamArgs {
     TreeArgs tree;         // reduction tree and final outputs
 };
 
+// 1 / x: the hardware estimate in FP32; in FP64 the estimate refined by two
+// Newton steps (each squares the relative error).
 template <typename T> __device__ __forceinline__ T rcp_fast(T x);
 template <> __device__ __forceinline__ float rcp_fast<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double rcp_fast<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double rcp_fast<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float abs_t(float a) { return __builtin_fabsf(a); }
@@ -45,8 +53,13 @@ template <typename T> __device__ __forceinline__ T sqrt_t(T x);
 template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return __builtin_sqrtf(x); }
 template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return __builtin_sqrt(x); }
 
+// T: arithmetic of the block (its dot products and updates); TI: input
+// element type; R, alpha, sigma and the reflector scalars are kept in FP64
+// (TR), so that the running factor of a long slab does not accumulate FP32
+// rounding from block to block.
 template <typename T, typename TI, int N, int RPL> struct Small {
     static_assert(N >= 1 && N <= 32, "small kernel covers 1..32 columns");
+    using TR = double;
     static constexpr int BR = 64 * RPL;                   // rows per block
     static constexpr int PN = ilog2(pow2ceil(N));         // butterfly order of n values
     static constexpr int roff(int j) {
@@ -57,7 +70,7 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     static constexpr int RS = roff(N);                    // R slots per wave (elements of T)
     static constexpr int SS = (N % 2) ? N : N + 1;        // staging row stride, odd -> no bank conflicts
     static constexpr int STG = 64 * SS;                   // staging elements (TI) per wave
-    static constexpr size_t r_bytes() { return (size_t)4 * RS * sizeof(T); }
+    static constexpr size_t r_bytes() { return (size_t)4 * RS * sizeof(TR); }
     static constexpr size_t stage_off() { return (r_bytes() + 15) & ~(size_t)15; }
     static constexpr size_t lds_bytes(bool staged) {  // per workgroup of 4 waves
         return stage_off() + (staged ? (size_t)4 * STG * sizeof(TI) : 0);
@@ -69,7 +82,7 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     // and every wave adds all W of them in wave order (the same sums in every
     // wave, so the W copies of R stay identical).
     template <int J, int W = 1>
-    static __device__ __forceinline__ void step(T (&x)[RPL][N], T* Rl, T* xchg = nullptr) {
+    static __device__ __forceinline__ void step(T (&x)[RPL][N], TR* Rl, T* xchg = nullptr) {
         if constexpr (J < N) {
             constexpr int CNT = N - J;
             constexpr int V = pow2ceil(CNT);
@@ -98,27 +111,29 @@ template <typename T, typename TI, int N, int RPL> struct Small {
                 for (int q = 1; q < W; ++q) D += xb[q * 64 + L];
             }
             const int vi = bfly_vidx<P>(L);
-            T* row = Rl + roff(J);
-            const T rj = row[vi];                    // R(J, J + vi), zero in padding slots
-            const T sigma = lane_bcast(D, 0);
-            const T alpha = lane_bcast(rj, 0);
-            const T nrm = sqrt_t<T>(fma_t(alpha, alpha, sigma));
-            const bool live = sigma != T(0);
-            const T beta = live ? (alpha >= T(0) ? -nrm : nrm) : alpha;
-            const T inv_beta = rcp_fast<T>(beta);
-            const T s = live ? rcp_fast<T>(alpha - beta) : T(0);        // 1 / (alpha - beta)
-            const T tau = live ? (beta - alpha) * inv_beta : T(0);
-            const T c = live ? inv_beta : T(0);                          // = -tau * s
-            const T w = fma_t(s, D, rj);
-            T rn = fma_t(-tau, w, rj);
+            TR* row = Rl + roff(J);
+            const TR rj = row[vi];                   // R(J, J + vi), zero in padding slots
+            const TR DR = (TR)D;
+            const TR sigma = lane_bcast(DR, 0);
+            const TR alpha = lane_bcast(rj, 0);
+            const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
+            const bool live = sigma != TR(0);
+            const TR beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
+            const TR inv_beta = rcp_fast<TR>(beta);
+            const TR s = live ? rcp_fast<TR>(alpha - beta) : TR(0);       // 1 / (alpha - beta)
+            const TR tau = live ? (beta - alpha) * inv_beta : TR(0);
+            const T c = live ? (T)inv_beta : T(0);                        // = -tau * s
+            const TR w = fma_t(s, DR, rj);
+            TR rn = fma_t(-tau, w, rj);
             if (vi == 0) rn = beta;
             row[vi] = rn;
+            const T wt = (T)w;
             T t[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) t[r] = c * x[r][J];
 #pragma unroll
             for (int v = 1; v < CNT; ++v) {
-                const T wk = lane_bcast(w, bfly_lane(v, P));
+                const T wk = lane_bcast(wt, bfly_lane(v, P));
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
             }
@@ -207,10 +222,10 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
     const int L = lane_id();
     const int64_t sid = (int64_t)blockIdx.x * 4 + wv;
     if (sid >= a.nstreams) return;                      // whole wave; no block barriers used
-    T* Rl = (T*)smem + wv * S::RS;
+    double* Rl = (double*)smem + wv * S::RS;
     TI* St = (TI*)(smem + S::stage_off()) + wv * S::STG;
 
-    for (int i = L; i < S::RS; i += 64) Rl[i] = T(0);
+    for (int i = L; i < S::RS; i += 64) Rl[i] = 0.0;
     wave_lds_sync();
 
     const int64_t r0 = sid * a.slab;
@@ -228,7 +243,7 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
     double* out = a.tree.nodes + sid * (int64_t)N * N;
     int off = 0;
     for (int j = 0; j < N; ++j) {
-        if (L < N) out[j * N + L] = L >= j ? (double)Rl[off + (L - j)] : 0.0;
+        if (L < N) out[j * N + L] = L >= j ? Rl[off + (L - j)] : 0.0;
         off += pow2ceil(N - j);
     }
     int src = 0;                                        // lane holding column L's sum
@@ -327,11 +342,11 @@ __global__ void __launch_bounds__(512) tsqr_coop_tree_kernel(TreeArgs t) {
             }
             if (L < N) t.node_cs[(nbase + group) * N + L] = cs;
         }
+        grid_release();       // each wave releases its own stores (only wave 0 wrote here)
         __syncthreads();
         const int64_t ngroup = group / G;
         const int gsize = (int)min((int64_t)G, ncount - ngroup * G);
         if (threadIdx.x == 0) {
-            grid_release();
             const int old = __hip_atomic_fetch_add(t.tickets + tbase + ngroup, 1, __ATOMIC_ACQ_REL,
                                                    __HIP_MEMORY_SCOPE_AGENT);
             const int last = old == gsize - 1;

@@ -1,0 +1,352 @@
+// Streaming Householder TSQR for 33..128 columns: W waves per slab, each wave
+// owning every W-th column (wave w holds columns w, w + W, ...; NW <= 32 per
+// wave) of the same 64 * RPL rows of a block.
+//
+// The algebra is that of the small kernel (structured Householder on
+// [R; B], tsqr_small.hpp), spread over waves by columns: at step j the wave
+// that owns column j publishes the pivot column B(:, j) and alpha = R(j, j)
+// through LDS (double-buffered, one block barrier per step); every wave forms
+// sigma = ||B(:, j)||^2 with one all-reduce, the dot products with its own
+// columns with one reduce-scatter butterfly, applies the reflector to its own
+// columns and keeps its own part of R(j, :) in LDS.  All waves use the same
+// sigma and alpha, so the reflector is identical in every wave.  The step
+// index runs in a loop (the pivot is read with a uniform register index), so
+// the code size does not grow with n.
+#pragma once
+#include "tsqr_small.hpp"
+
+namespace tsnmf {
+
+struct WideArgs {
+    const void* X;
+    int64_t m;
+    int64_t ld;
+    int64_t slab;
+    int64_t nstreams;
+    int32_t n;
+    int32_t pad_;
+    TreeArgs tree;
+};
+
+// R is kept in FP64 (like the small kernel), compactly: wave w stores, for
+// each row j, only its columns k >= j, i.e. local columns c0(j)..NW-1 with
+// c0(j) = ceil((j - w) / W) (0 for j <= w), row after row.
+template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
+    static constexpr int P = ilog2(NW);
+    static_assert((1 << P) == NW && NW <= 32, "NW must be a power of two <= 32");
+    static constexpr int BR = 64 * RPL;
+    static constexpr int NMAX = NW * W;
+    static constexpr int RW = NMAX * NW - W * NW * (NW - 1) / 2 + NMAX;   // FP64 slots per wave (bound)
+    static constexpr size_t pv_elems() { return (size_t)2 * (RPL * 64 + 1); } // two pivot slots (T)
+    static constexpr size_t lds_bytes() { return ((size_t)W * RW + 2) * 8 + pv_elems() * sizeof(T); }
+};
+
+template <int W> __device__ __forceinline__ int offw_me(const int (&offw)[W], int wv) {
+    int off = offw[0];
+#pragma unroll
+    for (int u = 1; u < W; ++u) off = (u == wv) ? offw[u] : off;
+    return off;
+}
+
+template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
+__global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
+    using S = Wide<T, TI, NW, W, RPL>;
+    constexpr int P = S::P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wv = (int)(threadIdx.x >> 6);
+    const int L = lane_id();
+    const int n = a.n;
+    const int64_t sid = blockIdx.x;
+    double* Rw = (double*)smem + (size_t)wv * S::RW;  // this wave's part of R (compact rows)
+    double* apub = (double*)smem + (size_t)W * S::RW;  // alpha of steps j (two slots by parity)
+    T* pv = (T*)(apub + 2);
+
+    for (int i = L; i < S::RW; i += 64) Rw[i] = 0.0;
+    const int vi = bfly_vidx<P>(L);                  // local column held by this lane after a butterfly
+    const int kcol = wv + W * vi;                    // its global column
+
+    const int64_t r0 = sid * a.slab;
+    const int64_t r1 = min(a.m, r0 + a.slab);
+    const TI* X = (const TI*)a.X;
+    double acc = 0.0;
+    __syncthreads();
+    for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
+        T x[RPL][NW];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int64_t i = b0 + r * 64 + L;
+            const bool ok = i < r1;
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const int k = wv + W * c;
+                const bool okc = ok && k < n;
+                const TI* p = LOAD == LOAD_COL ? X + min(i, a.m - 1) + (int64_t)min(k, n - 1) * a.ld
+                                               : X + min(i, a.m - 1) * a.ld + min(k, n - 1);
+                const TI v = LOAD == LOAD_COL ? __builtin_nontemporal_load(p) : *p;
+                x[r][c] = okc ? (T)v : T(0);
+            }
+        }
+        {   // l1 column sums of the block, own columns
+            T p[NW];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                T s = abs_t(x[0][c]);
+#pragma unroll
+                for (int r = 1; r < RPL; ++r) s += abs_t(x[r][c]);
+                p[c] = s;
+            }
+            acc += (double)butterfly<P>(p);
+        }
+        int offw[W];                                 // start of row j in each wave's storage
+#pragma unroll
+        for (int u = 0; u < W; ++u) offw[u] = 0;
+        for (int j = 0; j < n; ++j) {
+            const int o = j % W;
+            const int q = j / W;
+            const int c0 = j > wv ? (j - wv + W - 1) / W : 0;   // first local column with k >= j
+            T* slot = pv + (j & 1) * (RPL * 64 + 1);
+            if (wv == o) {
+                // pivot column q of this wave, picked with uniform selects
+                // (a variable register index would move x to scratch memory)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    T v = x[r][0];
+#pragma unroll
+                    for (int c = 1; c < NW; ++c) v = (c == q) ? x[r][c] : v;
+                    slot[r * 64 + L] = v;
+                }
+                // R(j, j) is the first entry of the owner's row j; it is
+                // overwritten in this step, so it is published before the barrier
+                if (L == 0) apub[j & 1] = Rw[offw_me(offw, wv)];
+            }
+            __syncthreads();
+            int off = offw[0];
+#pragma unroll
+            for (int u = 1; u < W; ++u) off = (u == wv) ? offw[u] : off;
+            T xp[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) xp[r] = slot[r * 64 + L];
+            const double alpha = apub[j & 1];        // R(j, j), published by the owner
+            T sg = xp[0] * xp[0];
+#pragma unroll
+            for (int r = 1; r < RPL; ++r) sg = fma_t(xp[r], xp[r], sg);
+            const double sigma = (double)wave_sum(sg);
+            T p[NW];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                T s = xp[0] * x[0][c];
+#pragma unroll
+                for (int r = 1; r < RPL; ++r) s = fma_t(xp[r], x[r][c], s);
+                p[c] = s;
+            }
+            const T D = butterfly<P>(p);
+            const bool mine = vi >= c0;              // this lane's column k satisfies k >= j
+            const double rj = mine ? Rw[off + vi - c0] : 0.0;
+            const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
+            const bool live = sigma != 0.0;
+            const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+            const double inv_beta = rcp_fast<double>(beta);
+            const double s = live ? rcp_fast<double>(alpha - beta) : 0.0;
+            const double tau = live ? (beta - alpha) * inv_beta : 0.0;
+            const T cb = live ? (T)inv_beta : T(0);
+            // Columns left of j are finished.  Their registers keep being
+            // transformed (harmlessly: their w only ever updates themselves),
+            // and their part of R is not written any more.
+            double w = __builtin_fma(s, (double)D, rj);
+            if (kcol == j) w = -beta;
+            double rn = __builtin_fma(-tau, w, rj);
+            if (kcol == j) rn = beta;
+            if (mine) Rw[off + vi - c0] = rn;
+            const T wt = (T)w;
+            T t[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) t[r] = cb * xp[r];
+#pragma unroll
+            for (int c = 0; c < NW; ++c) {
+                const T wk = lane_bcast(wt, bfly_lane(c, P));
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) x[r][c] = fma_t(t[r], wk, x[r][c]);
+            }
+#pragma unroll
+            for (int u = 0; u < W; ++u) offw[u] += NW - (j > u ? (j - u + W - 1) / W : 0);
+        }
+    }
+    __syncthreads();
+    // leaf node: row-major n x n FP64, zeros below the diagonal
+    double* out = a.tree.nodes + sid * (int64_t)n * n;
+    int off = 0;
+    for (int j = 0; j < n; ++j) {
+        const int c0 = j > wv ? (j - wv + W - 1) / W : 0;
+        if (L < NW) {
+            const int k = wv + W * L;
+            if (k < n) out[(int64_t)j * n + k] = L >= c0 ? Rw[off + L - c0] : 0.0;
+        }
+        off += NW - c0;
+    }
+    int src = 0;                                     // lane holding local column L's sum
+    for (int s2 = 0; s2 < P; ++s2) src |= ((L >> s2) & 1) << (5 - s2);
+    const double v = lane_gather(acc, src);
+    if (L < NW && wv + W * L < n) a.tree.node_cs[sid * n + wv + W * L] = v;
+}
+
+}  // namespace tsnmf
+
+namespace tsnmf {
+
+// ---- FP64 tree for wide factors ------------------------------------------------
+//
+// Binary tree over the leaf nodes; a workgroup of W waves merges one pair
+// (QR of [A; B], both upper triangular n x n) and climbs by ticket.  Column k
+// belongs to a group of QL = 64 W / NMAX lanes; lane g of the group holds rows
+// g, g + QL, ... of column k of A and of B.  At step j the group of column j
+// stores B(:, j) and A(j, j) in LDS; after a block barrier every lane reads the
+// entries of its own rows, forms partial sums of ||B(:, j)||^2 and of
+// B(:, j)^T B(:, k) over those rows, and the group adds them (DPP within the
+// quad), so every group holds the same sigma.  The lane holding A(j, k)
+// computes w_k = A(j, k) + dot_k / (alpha - beta), shares it with its group,
+// and the group updates its rows of B(:, k).  B(i, j) = 0 for i > j, so the
+// full-length sums are exact without masking.
+template <int NMAX, int W> struct TTWide {
+    static constexpr int QL = 64 * W / NMAX;     // lanes per column
+    static constexpr int RL = NMAX / QL;          // rows per lane
+    static_assert(QL == 4 || QL == 8, "four or eight lanes per column");
+};
+
+// Sum over aligned groups of QL lanes (every lane of the group gets it).
+template <int QL> __device__ __forceinline__ double group_sum(double x) {
+    x += dpp_read<kDppXor1>(x);
+    x += dpp_read<kDppXor2>(x);
+    if constexpr (QL == 8) x += dpp_read<kDppRowHalfMirror>(x);
+    return x;
+}
+
+template <int NMAX, int W>
+__global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int n) {
+    using TT = TTWide<NMAX, W>;
+    constexpr int QL = TT::QL, RL = TT::RL;
+    __shared__ double sy[NMAX + 1];
+    __shared__ int go;
+    const int tid = (int)threadIdx.x;
+    const int k = tid / QL;                 // column of this lane's group
+    const int g = tid % QL;                 // row class of this lane
+    const bool colok = k < n;
+    const int64_t nn = (int64_t)n * n;
+    const int kc = min(k, n - 1);
+
+    int64_t count = t.leaves;
+    int64_t base = 0, tbase = 0;
+    int64_t node = 2 * (int64_t)blockIdx.x;
+    double a[RL], b[RL];
+    bool first = true;
+    if (count == 1) node = 0;
+    while (count > 1) {
+        const int64_t parent = base + count + (node >> 1);
+        const int64_t pair = node >> 1;
+        // This workgroup may have written the node in the previous iteration
+        // with another thread-to-element mapping than the one used below.
+        __syncthreads();
+        if ((node | 1) >= count) {
+            // no partner: copy up
+            const double* src = t.nodes + (base + node) * nn;
+            double* dst = t.nodes + parent * nn;
+            for (int i = tid; i < n * n; i += W * 64) dst[i] = src[i];
+            for (int i = tid; i < n; i += W * 64) t.node_cs[parent * n + i] = t.node_cs[(base + node) * n + i];
+        } else {
+            if (!first) {
+                // Every wave wrote part of the node: each releases its own
+                // stores at agent scope before the barrier that precedes the
+                // ticket (a release by thread 0 alone would not cover them).
+                grid_release();
+                __syncthreads();
+                if (tid == 0) {
+                    const int old = __hip_atomic_fetch_add(t.tickets + tbase + pair, 1, __ATOMIC_ACQ_REL,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (old == 1)
+                        __hip_atomic_store(t.tickets + tbase + pair, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    go = old == 1;
+                }
+                __syncthreads();
+                if (!go) return;
+                grid_acquire();
+            }
+            const int64_t left = base + (node & ~(int64_t)1);
+            const double* A = t.nodes + left * nn;
+            const double* B = A + nn;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int i = min(g + QL * r, n - 1);
+                const bool ok = colok && g + QL * r < n;
+                a[r] = ok ? A[(int64_t)i * n + kc] : 0.0;
+                b[r] = ok ? B[(int64_t)i * n + kc] : 0.0;
+            }
+            for (int j = 0; j < n; ++j) {
+                __syncthreads();
+                if (k == j) {
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) sy[g + QL * r] = b[r];
+                    if (g == j % QL) sy[NMAX] = a[j / QL];
+                }
+                __syncthreads();
+                double sp = 0.0, dp = 0.0;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const double y = sy[g + QL * r];
+                    sp = __builtin_fma(y, y, sp);
+                    dp = __builtin_fma(y, b[r], dp);
+                }
+                const double alpha = sy[NMAX];
+                const double sigma = group_sum<QL>(sp);
+                const double dot = group_sum<QL>(dp);
+                const bool live = sigma != 0.0;
+                const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
+                const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+                const double s = live ? 1.0 / (alpha - beta) : 0.0;
+                const double cb = live ? 1.0 / beta : 0.0;
+                const double tau = (beta - alpha) * cb;
+                // A(j, k) sits in lane g == j % QL, register j / QL
+                double ajk = 0.0;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) ajk = (r == j / QL) ? a[r] : ajk;
+                double w = __builtin_fma(s, dot, ajk);
+                w = lane_gather(w, (tid & 63 & ~(QL - 1)) | (j % QL));   // the owner's value
+                if (k == j) w = -beta;
+                if (g == j % QL) {
+                    const double an = (k == j) ? beta : __builtin_fma(-tau, w, ajk);
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) a[r] = (r == j / QL) ? an : a[r];
+                }
+                const double cw = cb * w;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) b[r] = __builtin_fma(sy[g + QL * r], cw, b[r]);
+            }
+            double* dst = t.nodes + parent * nn;
+            if (colok) {
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const int i = g + QL * r;
+                    if (i < n) dst[(int64_t)i * n + k] = i <= k ? a[r] : 0.0;
+                }
+            }
+            for (int i = tid; i < n; i += W * 64)
+                t.node_cs[parent * n + i] = t.node_cs[left * n + i] + t.node_cs[(left + 1) * n + i];
+        }
+        first = false;
+        tbase += count >> 1;
+        base += count;
+        count = (count + 1) >> 1;
+        node >>= 1;
+    }
+    // root: final R (column-major), rows flipped to a nonnegative diagonal
+    __syncthreads();
+    const double* rootp = t.nodes + base * nn;
+    for (int i = tid; i < n * n; i += W * 64) {
+        const int r = i % n, c = i / n;          // R(r, c) at column-major i
+        const double d = rootp[(int64_t)r * n + r];
+        const double v = rootp[(int64_t)r * n + c];
+        t.R[i] = c >= r ? (d < 0.0 ? -v : v) : 0.0;
+    }
+    if (t.colsum != nullptr)
+        for (int i = tid; i < n; i += W * 64) t.colsum[i] = t.node_cs[base * n + i];
+}
+
+}  // namespace tsnmf

@@ -1,0 +1,9 @@
+// Wide TSQR kernels (33..128 columns): FP32 input widened to FP64, FP64 arithmetic, column-major.
+#include "tsqr_wide_inst.hpp"
+
+namespace tsnmf {
+hipError_t launch_wide_f32w_col(const WideArgs& a, hipStream_t stream) {
+    if (a.n <= 64) return launch_wide_w<double, float, 2, LOAD_COL>(a, stream);
+    return launch_wide_w<double, float, 4, LOAD_COL>(a, stream);
+}
+}  // namespace tsnmf

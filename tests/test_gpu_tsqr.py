@@ -190,3 +190,66 @@ def test_invalid_arguments(lib):
     assert lib.tsnmf_tsqr_r(X, 10, 300, 300, lib.F32, R) == 4
     bad = lib.TsqrConfig(leaf_rows=0, tree_arity=3, rows_per_lane=0)
     assert lib.tsnmf_tsqr_r_ex(X, 10, 4, 4, lib.F32, R, None, bad) == -8
+
+
+# ---- wide factors (33..128 columns) ------------------------------------------------
+
+@pytest.mark.parametrize("n", [33, 48, 64, 100, 128])
+def test_wide_fp32_rowmajor(lib, n):
+    m = 60_017
+    X = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=20, dist="uniform")
+    Rg, csg = _run(lib, X.cuda())
+    _check_against_oracle(Rg, csg, X.numpy(), 1e-6, 5e-5, 1e-6, norm_tol=1e-5)
+
+
+@pytest.mark.parametrize("n", [40, 64, 128])
+def test_wide_fp32_colmajor(lib, n):
+    m = 80_021
+    Xt = synth.random_matrix(n, m, dtype=torch.float32, seed_tag=21, dist="lognormal")
+    Rg, csg = _run(lib, Xt.cuda().t())
+    _check_against_oracle(Rg, csg, Xt.t().numpy(), 1e-6, 5e-5, 1e-6, norm_tol=1e-5)
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_wide_fp64(lib, n):
+    X = synth.random_matrix(40_000, n, dtype=torch.float64, seed_tag=22, dist="uniform")
+    Rg, csg = _run(lib, X.cuda())
+    _check_against_oracle(Rg, csg, X.numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
+
+
+def test_wide_fp32_input_fp64_leaves(lib):
+    X = synth.random_matrix(50_003, 96, dtype=torch.float32, seed_tag=23, dist="uniform")
+    Rg, csg = _run(lib, X.cuda(), leaf_f64=True)
+    _check_against_oracle(Rg, csg, X.numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
+
+
+def test_wide_tree_shapes(lib):
+    """Leaf counts 1, 2, 3, 5 and 37 exercise odd nodes at several levels."""
+    X = synth.random_matrix(30_000, 70, dtype=torch.float32, seed_tag=24).cuda()
+    Xh = X.cpu().numpy()
+    for leaf in [30_000, 15_000, 10_000, 6_000, 811]:
+        cfg = lib.TsqrConfig(leaf_rows=leaf, tree_arity=0, rows_per_lane=0)
+        Rg, csg = _run(lib, X, config=cfg)
+        _check_against_oracle(Rg, csg, Xh, 1e-6, 5e-5, 1e-6)
+
+
+def test_heat_transfer_tiled_full_size(lib):
+    """Heat-transfer shape at full size: 50,000,000 x 64 FP32 column-major
+    (12.8 GB) built as 1,000 copies of a 50,000 x 64 bump-sum block A, so that
+    R = sqrt(1000) R_A with R_A from the oracle, and colsum = 1000 d_A."""
+    blk = synth.heat_transfer(m=50_000, n=64, device="cuda")
+    A = blk["X"]                                  # (50000, 64) column-major view
+    t = 1000
+    store = A.t().contiguous().repeat(1, t)       # (64, 5e7): column-major X with ld = m
+    X = store.t()
+    Rg, csg = _run(lib, X)
+    del store, X
+    torch.cuda.empty_cache()
+    Ah = A.cpu().numpy().astype(np.float64)
+    ref = np.sqrt(t) * otsqr.tsqr_r_final(Ah, leaf_rows=5000)
+    gram = np.linalg.norm(Rg.T @ Rg - ref.T @ ref) / np.linalg.norm(ref) ** 2
+    assert gram <= 1e-6
+    cn = np.linalg.norm(ref, axis=0)
+    assert np.max(np.abs(np.linalg.norm(Rg, axis=0) - cn) / cn) <= 1e-5
+    dA = np.abs(Ah).sum(0)
+    assert np.max(np.abs(csg - t * dA) / (t * dA)) <= 1e-6

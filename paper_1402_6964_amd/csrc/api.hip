@@ -129,12 +129,35 @@ int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags
     return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, nullptr, stream);
 }
 
+int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, int32_t k, uint64_t seed,
+                     int64_t row_offset, float* Y, double* colsum, hipStream_t stream) {
+    if (X == nullptr) return -1;
+    if (m < 1) return -2;
+    if (n < 1) return -3;
+    if (ld < n) return -4;
+    const uint32_t dt = flags & TSNMF_DTYPE_MASK;
+    const uint32_t mode = flags & (TSNMF_GP_MFMA_BF16 | TSNMF_GP_SIMD_F32);
+    if ((dt != TSNMF_F32 && dt != TSNMF_BF16) || (flags & TSNMF_COL_MAJOR) ||
+        mode == (TSNMF_GP_MFMA_BF16 | TSNMF_GP_SIMD_F32) || (dt == TSNMF_BF16 && mode == TSNMF_GP_SIMD_F32) ||
+        (flags & ~(TSNMF_DTYPE_MASK | TSNMF_GP_MFMA_BF16 | TSNMF_GP_SIMD_F32)) != 0)
+        return -5;
+    if (k < 4 || k > 4096 || (k % 4) != 0) return -6;
+    if (row_offset < 0) return -8;
+    if (Y == nullptr) return -9;
+    if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
+    return gauss_proj_impl(X, m, (int)n, ld, flags, k, seed, row_offset, Y, colsum, stream);
+}
+
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
     if (max_m < 0) return -1;
     if (max_n < 0 || max_n > TSNMF_MAX_N) return -2;
     if (max_k < 0 || max_k > 4096) return -3;
     size_t b = 0;
     if (max_m > 0 && max_n > 0) b = tsqr_workspace_bytes(max_m, max_n);
+    if (max_m > 0 && max_n > 0 && max_k > 0) {
+        const size_t g = gp_workspace_bytes(max_m, max_n, max_k);
+        b = b > g ? b : g;
+    }
     return workspace_reserve(b);
 }
 

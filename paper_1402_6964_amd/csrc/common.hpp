@@ -42,6 +42,8 @@ int profile_record(int stage, hipEvent_t start, hipEvent_t stop);
 int profile_event(hipStream_t s, hipEvent_t* ev);
 
 // Implementations behind the C entry points (arguments already validated).
+int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
+                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
                 double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream);
 

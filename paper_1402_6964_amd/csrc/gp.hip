@@ -1,0 +1,333 @@
+// Gaussian projection Y = G^T X (Sec. 2.3; Sec. 3.2 / Algorithm 1) with G
+// generated on the fly and never stored.
+//
+// G(i, l) is a fixed function of (seed, global row i, column l): Philox4x32
+// with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11) on counter
+// (i mod 2^32, i >> 32, l / 4, 0) and key (seed mod 2^32, seed >> 32) gives
+// four 32-bit words, turned into uniforms u = ((x >> 8) + 1) 2^-24 in (0, 1]
+// and into the normals of columns 4q .. 4q + 3 by Box-Muller.  The hardware
+// log2 / sqrt / sin / cos (sin and cos take revolutions, so 2 pi u needs no
+// multiply) are used; their error is below 1e-6 relative, far under the
+// BF16 rounding of the matrix-core path.
+//
+// Like Algorithm 1's combiner, each workgroup sums the outer products g_i x_i^T
+// of its rows (FP32 accumulation); a second kernel adds the workgroup partials
+// in FP64 in a fixed order (the reduce step) and writes Y (k x n, column-major).
+#include "common.hpp"
+#include "wave.hpp"
+
+namespace tsnmf {
+
+namespace {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t (&o)[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    o[0] = c0;
+    o[1] = c1;
+    o[2] = c2;
+    o[3] = c3;
+}
+
+// Four normals G(i, 4q + s), s = 0..3.
+__device__ __forceinline__ void gauss4(int64_t i, uint32_t q, uint32_t k0, uint32_t k1, float (&g)[4]) {
+    uint32_t x[4];
+    philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), q, 0u, k0, k1, x);
+    float u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = (float)((x[t] >> 8) + 1u) * 0x1p-24f;
+    const float ln2 = 0.693147180559945309f;
+#pragma unroll
+    for (int t = 0; t < 4; t += 2) {
+        const float rad = __builtin_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u[t]));
+        g[t] = rad * __builtin_amdgcn_cosf(u[t + 1]);
+        g[t + 1] = rad * __builtin_amdgcn_sinf(u[t + 1]);
+    }
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct GpArgs {
+    const void* X;
+    int64_t m;
+    int64_t ld;
+    int32_t n;
+    int32_t k;
+    uint32_t key0, key1;
+    int64_t row_offset;
+    int64_t rows_per_wg;
+    float* part;        // [grid.x][k][n] partial Y (only this workgroup's l-range is written)
+    double* part_cs;    // [grid.x][n] partial column sums, or nullptr
+};
+
+__device__ __forceinline__ float load_f32(const void* X, int64_t idx, bool bf16) {
+    if (bf16) {
+        const uint16_t v = ((const uint16_t*)X)[idx];
+        return __uint_as_float((uint32_t)v << 16);
+    }
+    return __builtin_nontemporal_load((const float*)X + idx);
+}
+
+// ---- matrix-core path ------------------------------------------------------------
+//
+// Workgroup = 8 waves; grid.y selects a 512-wide l-range and wave w its
+// 64-wide slice (16 groups q of 4 columns).  Rows are taken 32 at a time (the
+// K of one 16x16x32 BF16 MFMA).  Lane L generates the Philox block of
+// (row i0 + 8 (L / 16) + t, group q = qbase + (L % 16)) for t = 0..7: its four
+// normals go to four different M-tiles (tile s holds columns 4q + s), so every
+// normal is used once.  The 32 x n chunk of X is staged in LDS as BF16,
+// column by column, so that the B operand of lane L (8 consecutive rows of one
+// column) is one 16-byte read.
+constexpr int kMfmaRows = 32;
+
+__global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
+    __shared__ __align__(16) __bf16 xs[128 * kMfmaRows];   // [column][row]
+    __shared__ double cs_sh[4][128];
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, L = tid & 63;
+    const int n = a.n, k = a.k;
+    const int NT = (n + 15) / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
+    const int lbase = blockIdx.y * 512 + wv * 64;    // first column l of this wave
+    const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
+    floatx4 acc[4][8];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    double csum = 0.0;                               // sums of column col_ld over this thread's rows
+    const int col_ld = tid & 127;                    // staging: column handled by this thread
+    const int rgrp = tid >> 7;                       // rows 8 rgrp .. 8 rgrp + 7 of the chunk
+    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows) {
+        __syncthreads();
+        if (col_ld < n) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int64_t i = i0 + rgrp * 8 + t;
+                const float v = i < r1 ? load_f32(a.X, i * a.ld + col_ld, bf16_in) : 0.0f;
+                csum += (double)__builtin_fabsf(v);
+                xs[col_ld * kMfmaRows + rgrp * 8 + t] = (__bf16)v;   // round to nearest even
+            }
+        }
+        __syncthreads();
+        bf16x8 av[4];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float g[4];
+            gauss4(a.row_offset + i0 + 8 * (L >> 4) + t, q, a.key0, a.key1, g);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s][t] = (__bf16)g[s];
+        }
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            if (nt < NT) {
+                const int c = nt * 16 + (L & 15);
+                const bf16x8 b = c < n ? *(const bf16x8*)(xs + c * kMfmaRows + 8 * (L >> 4)) : bf16x8{};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], b, acc[s][nt], 0, 0, 0);
+            }
+        }
+    }
+    // partial Y: tile (s, nt), element (row rho = 4 (L / 16) + e, column L % 16)
+    float* P = a.part + (int64_t)blockIdx.x * k * n;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            const int c = nt * 16 + (L & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int l = 4 * ((lbase >> 2) + 4 * (L >> 4) + e) + s;
+                if (nt < NT && c < n && l < k) P[(int64_t)l * n + c] = acc[s][nt][e];
+            }
+        }
+    if (a.part_cs != nullptr && blockIdx.y == 0) {
+        cs_sh[rgrp][col_ld] = csum;
+        __syncthreads();
+        if (tid < n) a.part_cs[(int64_t)blockIdx.x * n + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+    }
+}
+
+// ---- vector-ALU path (FP32) ---------------------------------------------------------
+//
+// Workgroup = 8 waves; grid.y selects a 512-wide l-range.  Wave w owns columns
+// 16 w .. 16 w + 15 of Y, lane L the groups q = qbase + L and qbase + 64 + L
+// (8 columns l), so a lane accumulates an 8 x 16 tile in FP32.  Rows go 4 at
+// a time: the 512 threads generate the 4 x 512 block of G (one Philox call
+// each) and stage the 4 x n rows of X in LDS; every lane then reads its 8 G
+// values and the wave's 16 X values (one broadcast) per row.
+constexpr int kSimdRows = 4;
+
+__global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
+    __shared__ __align__(16) float gs[2][kSimdRows][512];
+    __shared__ __align__(16) float xsm[2][kSimdRows][128];
+    __shared__ double cs_sh[4][128];
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, L = tid & 63;
+    const int n = a.n, k = a.k;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
+    const int lbase = blockIdx.y * 512;
+    float acc[8][16];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[e][c] = 0.0f;
+    double csum = 0.0;
+    const int gen_row = tid >> 7, gen_q = tid & 127;   // G generation: row and group of this thread
+    int buf = 0;
+    for (int64_t i0 = r0; i0 < r1; i0 += kSimdRows, buf ^= 1) {
+        {
+            float g[4];
+            gauss4(a.row_offset + i0 + gen_row, (uint32_t)((lbase >> 2) + gen_q), a.key0, a.key1, g);
+            *(float4*)&gs[buf][gen_row][4 * gen_q] = make_float4(g[0], g[1], g[2], g[3]);
+            if (tid < kSimdRows * 128) {
+                const int rr = tid >> 7, c = tid & 127;
+                const int64_t i = i0 + rr;
+                float v = 0.0f;
+                if (c < n && i < r1) v = load_f32(a.X, i * a.ld + c, false);
+                csum += (double)__builtin_fabsf(v);
+                xsm[buf][rr][c] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < kSimdRows; ++rr) {
+            const float4 ga = *(const float4*)&gs[buf][rr][4 * L];
+            const float4 gb = *(const float4*)&gs[buf][rr][256 + 4 * L];
+            const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+            float xv[16];
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+                const float4 t4 = *(const float4*)&xsm[buf][rr][16 * wv + 4 * c4];
+                xv[4 * c4] = t4.x;
+                xv[4 * c4 + 1] = t4.y;
+                xv[4 * c4 + 2] = t4.z;
+                xv[4 * c4 + 3] = t4.w;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) acc[e][c] = __builtin_fmaf(gv[e], xv[c], acc[e][c]);
+        }
+    }
+    float* P = a.part + (int64_t)blockIdx.x * k * n;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int l = lbase + (e < 4 ? 4 * L + e : 256 + 4 * L + (e - 4));
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int cc = 16 * wv + c;
+            if (cc < n && l < k) P[(int64_t)l * n + cc] = acc[e][c];
+        }
+    }
+    if (a.part_cs != nullptr && blockIdx.y == 0) {
+        if (tid < kSimdRows * 128) cs_sh[tid >> 7][tid & 127] = csum;
+        __syncthreads();
+        if (tid < n) a.part_cs[(int64_t)blockIdx.x * n + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+    }
+}
+
+// Sum of the workgroup partials in FP64, in workgroup order; Y column-major.
+__global__ void gp_reduce_kernel(const float* __restrict__ part, int64_t nparts, int k, int n, float* __restrict__ Y,
+                                 const double* __restrict__ part_cs, double* __restrict__ colsum) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // index l * n + c
+    if (t < (int64_t)k * n) {
+        double s = 0.0;
+        for (int64_t p = 0; p < nparts; ++p) s += (double)part[p * k * n + t];
+        const int l = (int)(t / n), c = (int)(t % n);
+        Y[(int64_t)c * k + l] = (float)s;
+    }
+    if (colsum != nullptr && t < n) {
+        double s = 0.0;
+        for (int64_t p = 0; p < nparts; ++p) s += part_cs[p * n + t];
+        colsum[t] = s;
+    }
+}
+
+constexpr int64_t kGpWorkgroups = 2048;
+
+int64_t gp_rows_per_wg(int64_t m, int rows_multiple) {
+    int64_t r = (m + kGpWorkgroups - 1) / kGpWorkgroups;
+    return ((r + rows_multiple - 1) / rows_multiple) * rows_multiple;
+}
+
+}  // namespace
+
+size_t gp_workspace_bytes(int64_t m, int n, int k) {
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    const int64_t parts = (m + rpw - 1) / rpw;
+    return kTicketBytes + (size_t)parts * k * n * 4 + (size_t)parts * n * 8 + 1024;
+}
+
+int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
+                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream) {
+    const bool bf16 = (flags & TSNMF_DTYPE_MASK) == TSNMF_BF16;
+    const bool mfma = bf16 || (flags & TSNMF_GP_MFMA_BF16) != 0;
+    const int rows_multiple = mfma ? kMfmaRows : kSimdRows;
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    const int64_t parts = (m + rpw - 1) / rpw;
+    void* ws = nullptr;
+    if (int st = workspace_get(gp_workspace_bytes(m, n, k), stream, &ws)) return st;
+    (void)rows_multiple;
+    GpArgs a{};
+    a.X = X;
+    a.m = m;
+    a.ld = ld;
+    a.n = n;
+    a.k = k;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.row_offset = row_offset;
+    a.rows_per_wg = rpw;
+    a.part = (float*)((char*)ws + kTicketBytes);
+    a.part_cs = colsum != nullptr ? (double*)((char*)ws + kTicketBytes + (size_t)parts * k * n * 4) : nullptr;
+    const dim3 grid((unsigned)parts, (unsigned)((k + 511) / 512));
+    const bool prof = profiling_on();
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    if (prof) {
+        if (int st = profile_event(stream, &e0)) return st;
+    }
+    if (mfma) {
+        hipLaunchKernelGGL(gp_mfma_kernel, grid, dim3(512), 0, stream, a, bf16 ? 1 : 0);
+    } else {
+        hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
+    }
+    TSNMF_LAUNCH_CHECK();
+    if (prof) {
+        if (int st = profile_event(stream, &e1)) return st;
+        if (int st = profile_event(stream, &e2)) return st;
+    }
+    const int64_t outs = (int64_t)k * n;
+    hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream, a.part, parts, k,
+                       n, Y, a.part_cs, colsum);
+    TSNMF_LAUNCH_CHECK();
+    if (prof) {
+        if (int st = profile_event(stream, &e3)) return st;
+        profile_record(0, e0, e1);
+        profile_record(1, e2, e3);
+    }
+    return TSNMF_OK;
+}
+
+}  // namespace tsnmf

@@ -148,6 +148,72 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
     return gauss_proj_impl(X, m, (int)n, ld, flags, k, seed, row_offset, Y, colsum, stream);
 }
 
+static const int kMaxSmall = 256;   // p, n bound of the n x n solvers
+static const int kMaxPicks = 64;    // r bound of XRAY and NNLS
+
+int tsnmf_select_spa(const double* M, int32_t p, int32_t n, int32_t ldm, const double* colscale, int32_t r,
+                     int32_t* K, double* score, int32_t* info, hipStream_t stream) {
+    if (M == nullptr) return -1;
+    if (p < 1 || p > kMaxSmall) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldm < p) return -4;
+    if (r < 1 || r > n) return -6;
+    if (K == nullptr) return -7;
+    if (info == nullptr) return -9;
+    return select_spa_impl(M, p, n, ldm, colscale, r, K, score, info, stream);
+}
+
+int tsnmf_select_xray(const double* M, int32_t p, int32_t n, int32_t ldm, int32_t r, int32_t* K, int32_t* info,
+                      hipStream_t stream) {
+    if (M == nullptr) return -1;
+    if (p < 1 || p > kMaxSmall) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldm < p) return -4;
+    if (r < 1 || r > n || r > kMaxPicks) return -5;
+    if (K == nullptr) return -6;
+    if (info == nullptr) return -7;
+    return select_xray_impl(M, p, n, ldm, r, K, info, stream);
+}
+
+int tsnmf_select_gp(const float* Y, int32_t k, int32_t n, int32_t ldy, const double* colscale, int32_t r,
+                    int32_t* K, int32_t* counts, int32_t* info, hipStream_t stream) {
+    if (Y == nullptr) return -1;
+    if (k < 1 || k > (1 << 20)) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldy < k) return -4;
+    if (r < 1 || r > n) return -6;
+    if (K == nullptr) return -7;
+    if (info == nullptr) return -9;
+    return select_gp_impl(Y, k, n, ldy, colscale, r, K, counts, info, stream);
+}
+
+int tsnmf_nnls(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t* K, int32_t r, double* H,
+               int32_t ldh, double* resid2, int32_t* info, hipStream_t stream) {
+    if (M == nullptr) return -1;
+    if (p < 1 || p > kMaxSmall) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldm < p) return -4;
+    if (K == nullptr) return -5;
+    if (r < 1 || r > n || r > kMaxPicks) return -6;
+    if (H == nullptr) return -7;
+    if (ldh < r) return -8;
+    return nnls_impl(M, p, n, ldm, K, r, H, ldh, resid2, info, stream);
+}
+
+int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t* K, int32_t r, const double* H,
+                   int32_t ldh, double* relerr, hipStream_t stream) {
+    if (M == nullptr) return -1;
+    if (p < 1 || p > kMaxSmall) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldm < p) return -4;
+    if (K == nullptr) return -5;
+    if (r < 1 || r > n) return -6;
+    if (H == nullptr) return -7;
+    if (ldh < r) return -8;
+    if (relerr == nullptr) return -9;
+    return residual_impl(M, p, n, ldm, K, r, H, ldh, relerr, stream);
+}
+
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
     if (max_m < 0) return -1;
     if (max_n < 0 || max_n > TSNMF_MAX_N) return -2;

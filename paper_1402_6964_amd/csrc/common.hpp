@@ -42,6 +42,15 @@ int profile_record(int stage, hipEvent_t start, hipEvent_t stop);
 int profile_event(hipStream_t s, hipEvent_t* ev);
 
 // Implementations behind the C entry points (arguments already validated).
+int select_spa_impl(const double* M, int p, int n, int ldm, const double* colscale, int r, int* K, double* score,
+                    int* info, hipStream_t stream);
+int select_gp_impl(const float* Y, int k, int n, int ldy, const double* colscale, int r, int* K, int* counts,
+                   int* info, hipStream_t stream);
+int select_xray_impl(const double* M, int p, int n, int ldm, int r, int* K, int* info, hipStream_t stream);
+int nnls_impl(const double* M, int p, int n, int ldm, const int* K, int r, double* H, int ldh, double* resid2,
+              int* info, hipStream_t stream);
+int residual_impl(const double* M, int p, int n, int ldm, const int* K, int r, const double* H, int ldh,
+                  double* relerr, hipStream_t stream);
 int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
                     int64_t row_offset, float* Y, double* colsum, hipStream_t stream);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,

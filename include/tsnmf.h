@@ -110,37 +110,47 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
 
 /* ---- batched thin QR ---------------------------------------------------------- */
 
-/* One matrix of a batch (host struct; the pointers inside are device pointers). */
-typedef struct tsnmf_matrix_desc {
-    const void* X;    /* m x n, layout and dtype from the plan's flags            */
-    int64_t m, n, ld; /* as in tsnmf_tsqr_r                                       */
-    double* R;        /* n x n FP64 column-major output                           */
-    double* colsum;   /* FP64[n] output or NULL                                   */
-} tsnmf_matrix_desc;
-
-typedef struct tsnmf_batch_plan_s* tsnmf_batch_plan;
+#define TSNMF_MAX_BATCH 4096
 
 /*
- * tsnmf_batch_plan_create: validate a batch of independent TSQR problems of
- * uneven m and n and build, on the device, the work list of one persistent
- * launch (one item per row slab, longest-first) plus the per-matrix reduction
- * trees.  Host call, synchronous, allocates; do it outside graph capture.
- *   batch  number of matrices, 1..65536
- *   desc   host array of `batch` descriptors
- *   flags  TSNMF_F32 (FP32 row blocks, FP64 trees) with TSNMF_ROW_MAJOR
- *   plan   host output handle
+ * tsnmf_tsqr_r_batched: R factors and l1 column sums of `batch` independent
+ * tall-and-skinny matrices of uneven shape in one persistent launch.  The
+ * paper has no batching; each matrix is treated as in tsnmf_tsqr_r (row
+ * splits as the independent map tasks of Sec. 3.5, FP64 reduction of their
+ * stacked R factors), and all matrices share one device work list.
+ *   batch   number of matrices, 1..TSNMF_MAX_BATCH (host value).
+ *   X       device array of `batch` device pointers, FP32 row-major matrices.
+ *   m, n, ld  device arrays of `batch` int64: rows, columns, leading
+ *           dimension of each matrix (1 <= n <= TSNMF_MAX_N, m >= 1, ld >= n).
+ *   flags   TSNMF_F32 (row-major); FP32 row blocks, FP64 R and trees.
+ *   R       device array of `batch` device pointers to n x n FP64
+ *           column-major outputs (diag(R) >= 0, R^T R = X^T X).
+ *   colsum  device array of `batch` device pointers to FP64[n] outputs (an
+ *           entry may be NULL), or NULL for no column sums.
+ * The arrays are read on the device when the work runs, so a captured graph
+ * may be replayed with new pointers and shapes in the same arrays.  A matrix
+ * whose entry is invalid (NULL X or R, n outside 1..TSNMF_MAX_N, m < 1,
+ * ld < n) is skipped; its R and column sums are set to NaN when R is not NULL
+ * and n is in range.  Matrices are scheduled largest-first by m n^2.
+ * Workspace: outside capture the call reads m, n and ld back (a host
+ * synchronisation on `stream`) and grows its own device workspace as needed;
+ * while capturing it uses what tsnmf_reserve_batched (or an earlier call)
+ * provided and returns TSNMF_ERR_CAPTURE if that cannot hold `batch`
+ * matrices.  With less tree storage than the default slabs need, the device
+ * doubles every slab until the trees fit (fewer, longer slabs; same result
+ * up to rounding).  Calls must not overlap on one device.
+ * Returns -1 (batch), -2 (X), -3 (m), -4 (n), -5 (ld), -6 (flags), -7 (R).
  */
-int tsnmf_batch_plan_create(int32_t batch, const tsnmf_matrix_desc* desc, uint32_t flags,
-                            tsnmf_batch_plan* plan);
+int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
+                         const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
+                         hipStream_t stream);
 
-/* Enqueue the whole batch: one persistent kernel over all row slabs of all
-   matrices, then the reduction trees and the finalisation of every R.  Makes no
-   allocation and no host synchronisation, so it can be captured into a HIP
-   graph and replayed; the X, R and colsum buffers named in the plan are used. */
-int tsnmf_tsqr_r_batched(tsnmf_batch_plan plan, hipStream_t stream);
-
-/* Free a plan (host call; the caller must ensure no enqueued use is pending). */
-int tsnmf_batch_plan_destroy(tsnmf_batch_plan plan);
+/* Reserve the batched workspace for up to `max_batch` matrices with at most
+   `max_rows` rows in total, at the default slab heights for any widths, so
+   that tsnmf_tsqr_r_batched can be captured into a graph.  Host call,
+   synchronous.  Returns -1 (max_batch outside 1..TSNMF_MAX_BATCH), -2
+   (max_rows < 0). */
+int tsnmf_reserve_batched(int32_t max_batch, int64_t max_rows);
 
 /* ---- Gaussian projection -------------------------------------------------------- */
 
@@ -243,10 +253,12 @@ int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
 
 /* Profiling aid.  While enabled (on != 0), TSQR and projection calls record
    HIP events on their stream around their main kernel ("stage 0": the leaf /
-   projection kernel) and around the rest of the call ("stage 1": reduction
-   tree and finalisation).  tsnmf_profile_query waits for the recorded events
-   (host synchronisation), returns the summed elapsed milliseconds and the
-   number of calls of a stage, and clears that stage.  Not for graph capture. */
+   projection kernel; for the batched call the persistent kernel, trees
+   included) and around the rest of the call ("stage 1": reduction tree and
+   finalisation; for the batched call the device planner).
+   tsnmf_profile_query waits for the recorded events (host synchronisation),
+   returns the summed elapsed milliseconds and the number of calls of a
+   stage, and clears that stage.  Not for graph capture. */
 int tsnmf_profile_enable(int on);
 int tsnmf_profile_query(int stage, double* total_ms, int64_t* calls);
 

@@ -65,6 +65,36 @@ int profile_event(hipStream_t s, hipEvent_t* ev) {
     return TSNMF_OK;
 }
 
+namespace {
+thread_local hipEvent_t g_split[2] = {nullptr, nullptr};
+}
+
+void profile_split(hipStream_t s) {
+    if (!g_prof_on) return;
+    for (auto& e : g_split) {
+        if (e != nullptr) (void)hipEventDestroy(e);
+        e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, s) != hipSuccess) {
+            (void)hipGetLastError();
+            if (e != nullptr) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    }
+}
+
+bool profile_take_split(hipEvent_t* end0, hipEvent_t* begin1) {
+    const bool ok = g_split[0] != nullptr && g_split[1] != nullptr;
+    if (ok) {
+        *end0 = g_split[0];
+        *begin1 = g_split[1];
+    } else {
+        for (auto& e : g_split)
+            if (e != nullptr) (void)hipEventDestroy(e);
+    }
+    g_split[0] = g_split[1] = nullptr;
+    return ok;
+}
+
 int profile_record(int stage, hipEvent_t start, hipEvent_t stop) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof[stage].pending.emplace_back(start, stop);
@@ -127,6 +157,25 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
 int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, double* R,
                  double* colsum, hipStream_t stream) {
     return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, nullptr, stream);
+}
+
+int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
+                         const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
+                         hipStream_t stream) {
+    if (batch < 1 || batch > TSNMF_MAX_BATCH) return -1;
+    if (X == nullptr) return -2;
+    if (m == nullptr) return -3;
+    if (n == nullptr) return -4;
+    if (ld == nullptr) return -5;
+    if (flags != TSNMF_F32) return -6;
+    if (R == nullptr) return -7;
+    return tsqr_batched_impl(batch, X, m, n, ld, R, colsum, stream);
+}
+
+int tsnmf_reserve_batched(int32_t max_batch, int64_t max_rows) {
+    if (max_batch < 1 || max_batch > TSNMF_MAX_BATCH) return -1;
+    if (max_rows < 0) return -2;
+    return batch_reserve(max_batch, max_rows);
 }
 
 int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, int32_t k, uint64_t seed,

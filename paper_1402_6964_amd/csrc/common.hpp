@@ -40,6 +40,11 @@ size_t gp_workspace_bytes(int64_t m, int n, int k);
 bool profiling_on();
 int profile_record(int stage, hipEvent_t start, hipEvent_t stop);
 int profile_event(hipStream_t s, hipEvent_t* ev);
+// Called by launch helpers between a leaf kernel and its tree kernel: while
+// profiling, records two events there (end of stage 0, start of stage 1) for
+// the caller to take with profile_take_split.
+void profile_split(hipStream_t s);
+bool profile_take_split(hipEvent_t* end0, hipEvent_t* begin1);
 
 // Implementations behind the C entry points (arguments already validated).
 int select_spa_impl(const double* M, int p, int n, int ldm, const double* colscale, int r, int* K, double* score,
@@ -53,6 +58,9 @@ int residual_impl(const double* M, int p, int n, int ldm, const int* K, int r, c
                   double* relerr, hipStream_t stream);
 int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
                     int64_t row_offset, float* Y, double* colsum, hipStream_t stream);
+int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const int64_t* n, const int64_t* ld,
+                      double* const* R, double* const* colsum, hipStream_t stream);
+int batch_reserve(int32_t max_batch, int64_t max_rows);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
                 double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream);
 

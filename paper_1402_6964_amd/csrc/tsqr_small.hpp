@@ -214,14 +214,12 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     }
 };
 
+// One wave factors slab `sid` of `a` and stores leaf node `sid`.  `smem` is the
+// workgroup's LDS laid out as in Small::lds_bytes, `wv` the wave's slot in it.
 template <typename T, typename TI, int N, int RPL, int LOAD>
-__global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
+__device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, unsigned char* smem, int wv) {
     using S = Small<T, TI, N, RPL>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int wv = (int)(threadIdx.x >> 6);
     const int L = lane_id();
-    const int64_t sid = (int64_t)blockIdx.x * 4 + wv;
-    if (sid >= a.nstreams) return;                      // whole wave; no block barriers used
     double* Rl = (double*)smem + wv * S::RS;
     TI* St = (TI*)(smem + S::stage_off()) + wv * S::STG;
 
@@ -252,6 +250,15 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
     if (L < N) a.tree.node_cs[sid * N + L] = v;
 }
 
+template <typename T, typename TI, int N, int RPL, int LOAD>
+__global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int wv = (int)(threadIdx.x >> 6);
+    const int64_t sid = (int64_t)blockIdx.x * 4 + wv;
+    if (sid >= a.nstreams) return;                      // whole wave; no block barriers used
+    small_slab<T, TI, N, RPL, LOAD>(a, sid, smem, wv);
+}
+
 // ---- FP64 reduction tree over the slab factors ---------------------------------
 //
 // One pass of a workgroup (8 waves) reduces a group of G consecutive nodes of
@@ -264,8 +271,8 @@ __global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
 // single node at the next level writes the final R (column-major, rows
 // flipped to a nonnegative diagonal) and the column sums.  Groups and orders
 // are fixed, so the result is deterministic.
-template <int N> struct CoopTree {
-    static constexpr int W = 8;                       // waves per workgroup
+template <int N, int W_ = 8> struct CoopTree {
+    static constexpr int W = W_;                      // waves per workgroup
     static constexpr int RPL = 2;                     // FP64 rows per lane
     static constexpr int CAP = W * 64 * RPL;          // rows per pass
     static constexpr int G = CAP / N < 64 ? CAP / N : 64;   // nodes per pass
@@ -280,20 +287,26 @@ template <int N> constexpr int64_t coop_tree_nodes(int64_t leaves) {
     return total + 1;
 }
 
-template <int N>
-__global__ void __launch_bounds__(512) tsqr_coop_tree_kernel(TreeArgs t) {
-    using CT = CoopTree<N>;
+template <int N, int W = 8> struct CoopTreeLds {
+    double sR[W][Small<double, double, N, CoopTree<N, W>::RPL>::RS];
+    double xchg[2 * W * 64];
+    int go;
+};
+
+// The whole workgroup (W waves) reduces group `group0` of level 0 and climbs.
+template <int N, int W = 8>
+__device__ __forceinline__ void coop_tree_run(const TreeArgs& t, int64_t group0, CoopTreeLds<N, W>& lds) {
+    using CT = CoopTree<N, W>;
     using S = Small<double, double, N, CT::RPL>;
     constexpr int G = CT::G;
     constexpr int64_t NN = (int64_t)N * N;
-    __shared__ double sR[CT::W][S::RS];
-    __shared__ double xchg[2 * CT::W * 64];
-    __shared__ int go;
+    double* xchg = lds.xchg;
+    int& go = lds.go;
     const int wv = (int)(threadIdx.x >> 6);
     const int L = lane_id();
-    double* Rl = sR[wv];
+    double* Rl = lds.sR[wv];
 
-    int64_t group = blockIdx.x;   // group index within the current level
+    int64_t group = group0;       // group index within the current level
     int64_t count = t.leaves;     // nodes at the current level
     int64_t base = 0;             // node offset of the current level
     int64_t tbase = 0;            // ticket offset of the next level
@@ -361,6 +374,12 @@ __global__ void __launch_bounds__(512) tsqr_coop_tree_kernel(TreeArgs t) {
         count = ncount;
         group = ngroup;
     }
+}
+
+template <int N>
+__global__ void __launch_bounds__(512) tsqr_coop_tree_kernel(TreeArgs t) {
+    __shared__ CoopTreeLds<N> lds;
+    coop_tree_run<N>(t, blockIdx.x, lds);
 }
 
 }  // namespace tsnmf

@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
 #include "tsqr_small.hpp"
 
 namespace tsnmf {
@@ -31,6 +32,7 @@ hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    profile_split(stream);
     // reduction tree: one workgroup per group of G leaves, later levels by ticket
     constexpr int G = CoopTree<N>::G;
     const int64_t groups = (a.tree.leaves + G - 1) / G;

@@ -48,15 +48,14 @@ template <int W> __device__ __forceinline__ int offw_me(const int (&offw)[W], in
     return off;
 }
 
+// The W waves of the workgroup factor slab `sid` of `a` and store leaf node `sid`.
 template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
-__global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
+__device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsigned char* smem) {
     using S = Wide<T, TI, NW, W, RPL>;
     constexpr int P = S::P;
-    extern __shared__ __align__(16) unsigned char smem[];
     const int wv = (int)(threadIdx.x >> 6);
     const int L = lane_id();
     const int n = a.n;
-    const int64_t sid = blockIdx.x;
     double* Rw = (double*)smem + (size_t)wv * S::RW;  // this wave's part of R (compact rows)
     double* apub = (double*)smem + (size_t)W * S::RW;  // alpha of steps j (two slots by parity)
     T* pv = (T*)(apub + 2);
@@ -186,7 +185,13 @@ __global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
     int src = 0;                                     // lane holding local column L's sum
     for (int s2 = 0; s2 < P; ++s2) src |= ((L >> s2) & 1) << (5 - s2);
     const double v = lane_gather(acc, src);
-    if (L < NW && wv + W * L < n) a.tree.node_cs[sid * n + wv + W * L] = v;
+    if (a.tree.node_cs != nullptr && L < NW && wv + W * L < n) a.tree.node_cs[sid * n + wv + W * L] = v;
+}
+
+template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
+__global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    wide_slab<T, TI, NW, W, RPL, LOAD>(a, blockIdx.x, smem);
 }
 
 }  // namespace tsnmf
@@ -220,12 +225,18 @@ template <int QL> __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+template <int NMAX> struct WideTreeLds {
+    double sy[NMAX + 1];
+    int go;
+};
+
+// The workgroup merges pair `pair0` of level 0 and climbs.
 template <int NMAX, int W>
-__global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int n) {
+__device__ __forceinline__ void wide_tree_run(const TreeArgs& t, int n, int64_t pair0, WideTreeLds<NMAX>& lds) {
     using TT = TTWide<NMAX, W>;
     constexpr int QL = TT::QL, RL = TT::RL;
-    __shared__ double sy[NMAX + 1];
-    __shared__ int go;
+    double* sy = lds.sy;
+    int& go = lds.go;
     const int tid = (int)threadIdx.x;
     const int k = tid / QL;                 // column of this lane's group
     const int g = tid % QL;                 // row class of this lane
@@ -235,7 +246,7 @@ __global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int 
 
     int64_t count = t.leaves;
     int64_t base = 0, tbase = 0;
-    int64_t node = 2 * (int64_t)blockIdx.x;
+    int64_t node = 2 * pair0;
     double a[RL], b[RL];
     bool first = true;
     if (count == 1) node = 0;
@@ -347,6 +358,12 @@ __global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int 
     }
     if (t.colsum != nullptr)
         for (int i = tid; i < n; i += W * 64) t.colsum[i] = t.node_cs[base * n + i];
+}
+
+template <int NMAX, int W>
+__global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int n) {
+    __shared__ WideTreeLds<NMAX> lds;
+    wide_tree_run<NMAX, W>(t, n, blockIdx.x, lds);
 }
 
 }  // namespace tsnmf

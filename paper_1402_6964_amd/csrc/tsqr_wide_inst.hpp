@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "common.hpp"
 #include "tsqr_wide.hpp"
 
 namespace tsnmf {
@@ -23,6 +24,7 @@ hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(kern, dim3((unsigned)a.nstreams), dim3(W * 64), lds, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    profile_split(stream);
     constexpr int NMAX = NW * W;
     constexpr int TW = NMAX <= 64 ? NMAX / 16 : NMAX / 8;    // 4 or 8 lanes per column
     const int64_t pairs = (a.tree.leaves + 1) / 2;

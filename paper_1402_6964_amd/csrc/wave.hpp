@@ -101,8 +101,21 @@ template <int BIT, typename T> __device__ __forceinline__ T allreduce_stage(T x)
     }
 }
 
-constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
-constexpr int pow2ceil(int v) { return v <= 1 ? 1 : 2 * pow2ceil((v + 1) >> 1); }
+// Loops rather than recursion: at run time a recursive constexpr function
+// becomes a real call with a stack frame.
+__host__ __device__ constexpr __forceinline__ int ilog2(int v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+__host__ __device__ constexpr __forceinline__ int pow2ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
 
 // One stage over the live values p[0 .. 2^(P - S) - 1]: S is the stage index
 // (0 = bit 5).  Pairs (p[2i], p[2i+1]) -> p[i] while values remain, then

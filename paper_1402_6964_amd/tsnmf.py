@@ -30,6 +30,7 @@ LEAF_F64 = 0x20
 GP_MFMA_BF16 = 0x100
 GP_SIMD_F32 = 0x200
 MAX_N = 128
+MAX_BATCH = 4096
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -42,10 +43,6 @@ class TsqrConfig(ctypes.Structure):
     _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32)]
 
 
-class MatrixDesc(ctypes.Structure):
-    _fields_ = [("X", _vp), ("m", _i64), ("n", _i64), ("ld", _i64), ("R", _vp), ("colsum", _vp)]
-
-
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -56,10 +53,8 @@ def _sig(name, res, args):
 _tsqr_r = _sig("tsnmf_tsqr_r", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
 _tsqr_r_ex = _sig("tsnmf_tsqr_r_ex", ctypes.c_int,
                   [_vp, _i64, _i64, _i64, _u32, _vp, _vp, ctypes.POINTER(TsqrConfig), _vp])
-_plan_create = _sig("tsnmf_batch_plan_create", ctypes.c_int,
-                    [_i32, ctypes.POINTER(MatrixDesc), _u32, ctypes.POINTER(_vp)])
-_tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_vp, _vp])
-_plan_destroy = _sig("tsnmf_batch_plan_destroy", ctypes.c_int, [_vp])
+_tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp])
+_reserve_batched = _sig("tsnmf_reserve_batched", ctypes.c_int, [_i32, _i64])
 _gauss_proj = _sig("tsnmf_gauss_proj", ctypes.c_int,
                    [_vp, _i64, _i64, _i64, _u32, _i32, _u64, _i64, _vp, _vp, _vp])
 _select_spa = _sig("tsnmf_select_spa", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp])
@@ -118,19 +113,13 @@ def tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):
     return _tsqr_r_ex(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), c, _stream(stream))
 
 
-def tsnmf_batch_plan_create(descs, flags):
-    arr = (MatrixDesc * len(descs))(*descs)
-    h = _vp()
-    st = _plan_create(len(descs), arr, flags, ctypes.byref(h))
-    return st, h
+def tsnmf_tsqr_r_batched(batch, X, m, n, ld, flags, R, colsum=None, stream=None):
+    return _tsqr_batched(batch, _ptr(X), _ptr(m), _ptr(n), _ptr(ld), flags, _ptr(R), _ptr(colsum),
+                         _stream(stream))
 
 
-def tsnmf_tsqr_r_batched(plan, stream=None):
-    return _tsqr_batched(plan, _stream(stream))
-
-
-def tsnmf_batch_plan_destroy(plan):
-    return _plan_destroy(plan)
+def tsnmf_reserve_batched(max_batch, max_rows):
+    return _reserve_batched(max_batch, max_rows)
 
 
 def tsnmf_gauss_proj(X, m, n, ld, flags, k, seed, row_offset, Y, colsum=None, stream=None):
@@ -297,3 +286,54 @@ def residual(M, K, H, stream=None):
 
 def reserve(max_m, max_n, max_k=0):
     _check("tsnmf_reserve", tsnmf_reserve(max_m, max_n, max_k))
+
+
+class Batch:
+    """Device arrays for tsnmf_tsqr_r_batched over a list of row-major FP32
+    CUDA matrices, with FP64 outputs allocated by torch.  ``run`` enqueues the
+    call; the arrays stay valid for replays of a captured graph."""
+
+    def __init__(self, mats, with_colsum=True):
+        if not mats:
+            raise ValueError("empty batch")
+        dev = mats[0].device
+        self.mats = list(mats)
+        lds = []
+        for X in self.mats:
+            lay, ld = _layout(X)
+            if lay != ROW_MAJOR or X.dtype != torch.float32:
+                raise ValueError("the batched call takes row-major float32 matrices")
+            lds.append(ld)
+        self.Rbuf = [torch.empty((X.shape[1], X.shape[1]), dtype=torch.float64, device=dev) for X in self.mats]
+        self.cs = [torch.empty(X.shape[1], dtype=torch.float64, device=dev) for X in self.mats] if with_colsum else None
+
+        def arr(vals):
+            return torch.tensor(vals, dtype=torch.int64).to(dev)
+
+        self.X = arr([X.data_ptr() for X in self.mats])
+        self.m = arr([X.shape[0] for X in self.mats])
+        self.n = arr([X.shape[1] for X in self.mats])
+        self.ld = arr(lds)
+        self.R = arr([r.data_ptr() for r in self.Rbuf])
+        self.colsum = arr([c.data_ptr() for c in self.cs]) if with_colsum else None
+
+    def run(self, stream=None):
+        _check("tsnmf_tsqr_r_batched",
+               tsnmf_tsqr_r_batched(len(self.mats), self.X, self.m, self.n, self.ld, F32, self.R, self.colsum,
+                                    stream))
+
+    def results(self):
+        """[(R, colsum)] with R the logical n x n view of each output."""
+        return [(colmajor_square(r), None if self.cs is None else c)
+                for r, c in zip(self.Rbuf, self.cs or [None] * len(self.Rbuf))]
+
+
+def tsqr_r_batched(mats, with_colsum=True, stream=None):
+    """R factors and column sums of a list of row-major FP32 CUDA matrices."""
+    b = Batch(mats, with_colsum)
+    b.run(stream)
+    return b.results()
+
+
+def reserve_batched(max_batch, max_rows):
+    _check("tsnmf_reserve_batched", tsnmf_reserve_batched(max_batch, max_rows))

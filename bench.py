@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of the single-pass TSQR hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 
 A step is one tsnmf_tsqr_r call on the flow-cytometry-shaped workload
 (10,000,000 x 25 FP32 row-major, 1.0 GB, synthetic near-separable data resident
@@ -14,7 +14,14 @@ divided by the mean step time).  The line also carries:
   cpu_baseline  the CPU oracle (plain FP64 numpy Householder TSQR) timed on a
                 bounded row sample of the same X on this host;
   r_error       ||R^T R - X^T X||_F / ||X||_F^2 and the column-norm error of
-                the benchmarked R against the oracle's reference sums of X.
+                the benchmarked R against the oracle's reference sums of X;
+  extras        the other hot-path workloads, each timed after the main steps
+                (skipped with --no-extras): the batched TSQR of 512 uneven
+                matrices (one graph-captured persistent launch, against one
+                FP64 tsnmf_tsqr_r call per matrix), the heat-transfer-shaped
+                50,000,000 x 64 column-major matrix, the 20,000,000 x 128
+                Gaussian projection (BF16 matrix cores and FP32 vector units),
+                and the 100,000 x 20 FP64 example.
 Only one GPU is used: --gpus above 1 exits with a message.
 """
 
@@ -43,6 +50,7 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and R check")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU oracle time")
+    ap.add_argument("--no-extras", action="store_true", help="time only the main workload")
     ap.add_argument("--copy-reference", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
@@ -112,6 +120,157 @@ def cpu_baseline(X_gpu, R_gpu, cs_gpu, target_s):
     return out
 
 
+def _note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _gram_error(R, X64):
+    import numpy as np
+    G = X64.T @ X64
+    return float(np.linalg.norm(R.T @ R - G) / np.trace(G))
+
+
+def extras(torch, tsnmf, synth, dev, check=True):
+    """The other hot-path workloads, a few timed repetitions each."""
+    import numpy as np
+    out = {}
+
+    # batched TSQR: 512 matrices, m log-uniform in [1e4, 2e6], n in {16, 32, 64, 128}
+    _note("batched: generating 512 matrices")
+    shapes = synth.batch_shapes()
+    mats = [synth.batch_matrix(q, m, n, device=dev)["X"] for q, (m, n) in enumerate(shapes)]
+    total_bytes = sum(m * n * 4 for m, n in shapes)
+    flops = sum(2.0 * m * n * n for m, n in shapes)
+    b = tsnmf.Batch(mats)
+    b.run()                                        # sizes the workspace outside capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    g.replay()
+    t_batch = _timed(torch, g.replay, 5)
+    _note(f"batched: {t_batch * 1e3:.2f} ms per batch; timing the per-matrix FP64 baseline")
+    # baseline: one FP64 tsnmf_tsqr_r call (leaf kernel + tree kernel) per matrix
+    Rs = [torch.empty((n, n), dtype=torch.float64, device=dev) for _, n in shapes]
+    css = [torch.empty(n, dtype=torch.float64, device=dev) for _, n in shapes]
+    stream = torch.cuda.current_stream(dev)
+    flags = tsnmf.F32 | tsnmf.LEAF_F64
+
+    def per_matrix():
+        for X, R, c in zip(mats, Rs, css):
+            st = tsnmf.tsnmf_tsqr_r(X, X.shape[0], X.shape[1], X.shape[1], flags, R, c, stream)
+            if st != 0:
+                raise tsnmf.TsnmfError("tsnmf_tsqr_r", st)
+
+    per_matrix()
+    t_base = _timed(torch, per_matrix, 2)
+    _note(f"batched: baseline {t_base * 1e3:.2f} ms per batch")
+    res = b.results()
+    # R error on one matrix per width (the shortest), against the FP64 reference sums
+    errs, agree = [], []
+    if check:
+        for n in (16, 32, 64, 128):
+            q = min((i for i, s in enumerate(shapes) if s[1] == n), key=lambda i: shapes[i][0])
+            X64 = mats[q].cpu().numpy().astype(np.float64)
+            Rb = res[q][0].cpu().numpy()
+            errs.append(_gram_error(Rb, X64))
+            Rf = tsnmf.colmajor_square(Rs[q]).cpu().numpy()
+            agree.append(float(np.abs(Rb - Rf).max() / np.abs(Rf).max()))
+    out["batched"] = {
+        "workload": "512 FP32 row-major matrices, m log-uniform in [1e4, 2e6], n in {16, 32, 64, 128}",
+        "matrices": len(shapes), "bytes": total_bytes, "flops": flops,
+        "ms_per_batch": round(t_batch * 1e3, 3),
+        "matrices_per_s": round(len(shapes) / t_batch, 1),
+        "gbs": round(total_bytes / t_batch / 1e9, 1),
+        "tflops_fp32": round(flops / t_batch / 1e12, 2),
+        "baseline_fp64_per_matrix_ms_per_batch": round(t_base * 1e3, 3),
+        "baseline_matrices_per_s": round(len(shapes) / t_base, 1),
+        "speedup_vs_baseline": round(t_base / t_batch, 2),
+        "gram_rel_max": max(errs) if errs else None, "gram_tol": 1e-6,
+        "max_rel_diff_vs_fp64_baseline": max(agree) if agree else None,
+        "graph_captured": True,
+    }
+    del mats, b, g, Rs, css, res
+    torch.cuda.empty_cache()
+
+    # heat-transfer-shaped matrix, column-major (ld = m)
+    _note("heat transfer: generating 50,000,000 x 64")
+    d = synth.heat_transfer(device=dev)
+    X = d["X"]
+    m, n = X.shape
+    R = torch.empty((n, n), dtype=torch.float64, device=dev)
+    c = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def heat():
+        st = tsnmf.tsnmf_tsqr_r(X, m, n, m, tsnmf.F32 | tsnmf.COL_MAJOR, R, c, stream)
+        if st != 0:
+            raise tsnmf.TsnmfError("tsnmf_tsqr_r", st)
+
+    heat()
+    tsnmf.tsnmf_profile_query(0)
+    tsnmf.tsnmf_profile_enable(True)
+    t = _timed(torch, heat, 5)
+    tsnmf.tsnmf_profile_enable(False)
+    _, lms, lcalls = tsnmf.tsnmf_profile_query(0)
+    tsnmf.tsnmf_profile_query(1)
+    hb = m * n * 4
+    out["heat_transfer"] = {"workload": "50,000,000 x 64 FP32 column-major (12.8 GB)", "ms": round(t * 1e3, 3),
+                            "gbs": round(hb / t / 1e9, 1),
+                            "leaf_gbs": round(hb / (lms / max(lcalls, 1) * 1e-3) / 1e9, 1)}
+    del X, d
+    torch.cuda.empty_cache()
+
+    # Gaussian projection Y = G^T X, k = 512
+    _note("projection: generating 20,000,000 x 128")
+    d = synth.projection(device=dev)
+    X = d["X"]
+    Xb = X.to(torch.bfloat16)
+    m, n = X.shape
+    k = 512
+    Y = torch.empty((n, k), dtype=torch.float32, device=dev)
+    proj = {}
+    for name, Xin, fl, peak in (("bf16_mfma", Xb, tsnmf.BF16 | tsnmf.GP_MFMA_BF16, 2500.0),
+                                ("fp32_simd", X, tsnmf.F32 | tsnmf.GP_SIMD_F32, 157.3)):
+        def gp():
+            st = tsnmf.tsnmf_gauss_proj(Xin, m, n, n, fl, k, 14026964, 0, Y, None, stream)
+            if st != 0:
+                raise tsnmf.TsnmfError("tsnmf_gauss_proj", st)
+        gp()
+        t = _timed(torch, gp, 3)
+        tf = 2.0 * m * n * k / t / 1e12
+        proj[name] = {"ms": round(t * 1e3, 3), "tflops": round(tf, 1), "peak_tflops": peak,
+                      "frac": round(tf / peak, 4), "gbs": round(Xin.numel() * Xin.element_size() / t / 1e9, 1)}
+    out["projection"] = {"workload": "20,000,000 x 128, k = 512", **proj}
+    del X, Xb, d, Y
+    torch.cuda.empty_cache()
+
+    # the 100,000 x 20 FP64 example (whole path in FP64)
+    d = synth.plain_fp64(device=dev)
+    X = d["X"]
+    m, n = X.shape
+    R = torch.empty((n, n), dtype=torch.float64, device=dev)
+
+    def small():
+        st = tsnmf.tsnmf_tsqr_r(X, m, n, n, tsnmf.F64, R, None, stream)
+        if st != 0:
+            raise tsnmf.TsnmfError("tsnmf_tsqr_r", st)
+
+    small()
+    t = _timed(torch, small, 20)
+    out["plain_fp64"] = {"workload": "100,000 x 20 FP64 row-major", "ms": round(t * 1e3, 4),
+                         "gbs": round(m * n * 8 / t / 1e9, 1)}
+    return out
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -133,6 +292,7 @@ def main():
         return
 
     wl = WORKLOAD
+    _note("main: generating 10,000,000 x 25")
     d = synth.flow_cytometry(m=wl["m"], n=wl["n"], r=wl["r"], device=dev)
     X = d["X"]
     m, n = X.shape
@@ -180,8 +340,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "flow_cytometry 10,000,000 x 25 FP32 row-major (1.0 GB), "
-                               "FP32 Householder leaves + FP64 tree", **wl},
+        "config": {**wl, "workload": "flow_cytometry 10,000,000 x 25 FP32 row-major (1.0 GB), "
+                                     "FP32 Householder leaves + FP64 tree"},
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -189,9 +349,15 @@ def main():
                      "algorithmic_bytes_per_launch": wl["bytes"]},
         "tail_avg_ms": round(tail_ms / max(tail_calls, 1), 5),
     }
+    _note(f"main: {ms_per_step:.4f} ms per step")
     if not args.no_cpu:
         torch.cuda.synchronize()
+        _note("cpu baseline: timing the oracle")
         line.update(cpu_baseline(X, tsnmf.colmajor_square(Rbuf), cs, args.cpu_seconds))
+    if not args.no_extras:
+        del X, d
+        torch.cuda.empty_cache()
+        line["extras"] = extras(torch, tsnmf, synth, dev, check=not args.no_cpu)
     print(json.dumps(line), flush=True)
 
 

@@ -15,7 +15,23 @@ import torch
 from oracle import gauss_proj, nnls, residual, select, tsqr
 from paper_1402_6964_amd import synth
 
-PLANTED = [0, 1] + [10 * i for i in range(2, 20)]
+import os
+
+
+def _golden():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sec4_synthetic_example.txt")
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                out[k] = v
+    return out
+
+
+GOLDEN = _golden()
+PLANTED = [int(v) for v in GOLDEN["extreme"]]
+XRAY_PICKS = int(GOLDEN["xray_picks_containing_all"][0])
 
 
 @pytest.fixture(scope="module", params=[False, True], ids=["exact", "noisy"])
@@ -28,7 +44,14 @@ def example(request):
 
 
 def test_planted_set_follows_the_swap_rule(example):
-    assert example["K"] == PLANTED        # {0, 1, 20, 30, ..., 190}: 20 columns
+    """The generator's extreme set is the one the swap rule of Sec. 4 gives."""
+    r = int(GOLDEN["r"][0])
+    lo, hi = int(GOLDEN["swap_first"][0]), int(GOLDEN["swap_last"][0])
+    perm = list(range(int(GOLDEN["n"][0])))
+    for i in range(lo, hi + 1):
+        perm[i], perm[10 * i] = perm[10 * i], perm[i]
+    assert sorted(perm.index(j) for j in range(r)) == PLANTED
+    assert example["K"] == PLANTED and len(PLANTED) == r
 
 
 def test_spa_recovers_all_extreme_columns(example):
@@ -62,5 +85,5 @@ def test_residual_vanishes_at_r20(example):
 def test_xray_first_21_picks_contain_the_extreme_columns(example):
     """The Fig. 2 caption and the Sec. 4 text disagree on XRAY; the text says
     the first 21 greedy picks contain all 20 extreme columns, and so they do."""
-    K, _ = select.xray(example["R"], 21)
+    K, _ = select.xray(example["R"], XRAY_PICKS)
     assert set(PLANTED) <= set(K)

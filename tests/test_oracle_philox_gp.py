@@ -42,6 +42,19 @@ def test_philox_matches_rocrand_block_function():
     assert np.array_equal(got, ref)
 
 
+def test_philox_known_answers():
+    """The published known-answer vectors of Philox4x32-10 (golden fixture)."""
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(v, 16) for v in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        got = [int(w) for w in philox.philox4x32_10(*r[:6])]
+        assert got == r[6:], f"counter/key {r[:6]}"
+
+
 def test_uniform_range_endpoints():
     u = philox.uniform_open0(np.array([0, 255, 256, 0xFFFFFFFF], dtype=np.uint64))
     assert u[0] == 2.0 ** -24 and u[1] == 2.0 ** -24 and u[2] == 2.0 ** -23 and u[3] == 1.0

@@ -29,7 +29,9 @@ def nnls(A, b, max_outer=None):
     largest w_j (ties -> smallest index) into P.  Inner loop: solve the
     unconstrained problem on P; if some component is <= 0, step from x toward
     that solution as far as feasibility allows, move the indices that hit zero
-    out of P, and repeat.  info = 1 when the outer-iteration cap (3 r) is hit.
+    out of P (at least the one that limits the step, so the inner loop ends
+    within |P| rounds), and repeat.  info = 1 when the outer-iteration cap
+    (3 r) is hit.
     """
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -60,9 +62,20 @@ def nnls(A, b, max_outer=None):
             if (s[idx] > 0).all():
                 x = s
                 break
+            # step length: the largest alpha keeping x + alpha (s - x) >= 0 on
+            # the indices whose unconstrained value is <= 0; an index already
+            # at zero (x_u = 0, e.g. the one that just entered) allows no step
             bad = idx[s[idx] <= 0]
-            alpha = np.min(x[bad] / (x[bad] - s[bad]))
-            x = x + alpha * (s - x)
+            if len(bad) == 0:                # NaN in the subproblem: no finite step
+                info = 1
+                break
+            xb = x[bad]
+            pos = xb > 0
+            ratios = np.zeros(len(bad))
+            ratios[pos] = xb[pos] / (xb[pos] - s[bad][pos])
+            k = int(np.argmin(ratios))
+            x = x + ratios[k] * (s - x)
+            x[bad[k]] = 0.0                  # the index that limits the step is at its bound
             drop = P & (x <= tol)
             x[drop] = 0.0
             P &= ~drop

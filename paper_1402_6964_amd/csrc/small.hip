@@ -321,6 +321,7 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
         if (outer >= maxit) { inf = 1; break; }
         ++outer;
         pass[tbest] = 1.0;
+        int inner = 0;
         while (true) {
             int qn = 0;
             for (int q = 0; q < r; ++q)
@@ -333,21 +334,31 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
                 for (int q = 0; q < r; ++q) x[q] = s[q];
                 break;
             }
+            // Largest step keeping x >= 0 over the indices with s <= 0.  An
+            // index already at zero (x = 0) allows no step: its ratio is 0,
+            // not 0 / 0.  The index that limits the step is set to zero and
+            // leaves P, so this loop ends within qn rounds.
             double alpha = DBL_MAX;
+            int ubest = -1;
             for (int q = 0; q < qn; ++q) {
                 const int u = idx[q];
                 if (s[u] <= 0.0) {
-                    const double al = x[u] / (x[u] - s[u]);
-                    alpha = al < alpha ? al : alpha;
+                    const double al = x[u] > 0.0 ? x[u] / (x[u] - s[u]) : 0.0;
+                    if (al < alpha) { alpha = al; ubest = u; }
                 }
             }
+            if (ubest < 0) {                 // no finite step (NaN in the subproblem)
+                inf = 1;
+                break;
+            }
             for (int q = 0; q < r; ++q) x[q] += alpha * (s[q] - x[q]);
+            x[ubest] = 0.0;
             int left = 0;
             for (int q = 0; q < r; ++q) {
                 if (pass[q] != 0.0 && x[q] <= tol) { pass[q] = 0.0; x[q] = 0.0; }
                 left += pass[q] != 0.0;
             }
-            if (left == 0) break;
+            if (left == 0 || ++inner > r) break;
         }
     }
     for (int q = 0; q < r; ++q) H[(int64_t)i * ldh + q] = x[q];

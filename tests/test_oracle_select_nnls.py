@@ -172,3 +172,33 @@ def test_residual_zero_at_planted_rank_and_positive_below():
     assert np.abs(Hr - H).max() <= 1e-10          # P9: planted H recovered
     Hs, _, _ = nnls.nnls_matrix(R, K[:3])
     assert residual.relative_residual(R, K[:3], Hs) > 1e-6
+
+
+@pytest.mark.timeout(60)
+def test_nnls_entering_index_with_zero_value_terminates(monkeypatch):
+    """Lawson-Hanson step length when the index that just entered gets an
+    unconstrained value of exactly zero (possible in rounding): its ratio is
+    0 (no step), not 0 / 0, and it leaves the passive set; the inner loop
+    ends and the result still satisfies the optimality conditions."""
+    from oracle import nnls as on
+    rng = np.random.default_rng(3)
+    A = rng.uniform(size=(30, 6))
+    b = A @ np.array([0.5, 0.0, 1.0, 0.0, 0.2, 0.0]) + 0.01 * rng.uniform(size=30)
+    real_ls = on._ls
+    calls = {"n": 0}
+
+    def ls_with_zero(Asub, rhs):
+        s = real_ls(Asub, rhs)
+        calls["n"] += 1
+        if calls["n"] >= 2:            # from the second subproblem on: last component exactly 0
+            s = s.copy()
+            s[-1] = 0.0
+        return s
+
+    monkeypatch.setattr(on, "_ls", ls_with_zero)
+    x, r2, info = on.nnls(A, b)
+    assert np.all(np.isfinite(x)) and np.all(x >= 0)
+    monkeypatch.setattr(on, "_ls", real_ls)
+    xr, _, _ = on.nnls(A, b)
+    assert on.kkt_violation(A, b, xr) <= 1e-10
+    assert info in (0, 1)

@@ -86,7 +86,12 @@ __host__ __device__ inline Sizes matrix_sizes(int64_t m, int64_t n, int c, int s
     Sizes s{};
     const int64_t br = class_block(c);
     const int64_t mr = (m + br - 1) / br * br;
-    const int64_t want = shift >= 40 ? mr : class_slab(c) << shift;
+    int64_t want = shift >= 40 ? mr : class_slab(c) << shift;
+    if (c == CLS_S16 || c == CLS_S32) {
+        // the one-wave kernel addresses a slab through a 32-bit byte range
+        const int64_t cap = kMaxBufSlabBytes / (n * 4) / br * br;
+        want = want < cap ? want : cap;
+    }
     s.slab = want < mr ? want : mr;
     s.leaves = (m + s.slab - 1) / s.slab;
     s.items = (s.leaves + class_per_item(c) - 1) / class_per_item(c);
@@ -176,6 +181,7 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
     const int chunk = (B + kPlanThreads - 1) / kPlanThreads;
     const int p0 = min(B, t * chunk), p1 = min(B, p0 + chunk);
     int shift = 0;
+    bool overflow = false;
     for (;; ++shift) {
         int64_t w = 0, k = 0;
         for (int p = p0; p < p1; ++p) {
@@ -188,7 +194,27 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
         int64_t wt = 0, kt = 0;
         (void)block_exclusive_scan(w, tmp, &wt);
         (void)block_exclusive_scan(k, tmp, &kt);
-        if ((wt <= dcap && kt <= tcap) || shift >= 40) break;
+        if ((wt <= dcap && kt <= tcap) || shift >= 40) {
+            overflow = wt > dcap || kt > tcap;
+            break;
+        }
+    }
+    if (overflow) {
+        // The trees do not fit even at the longest slabs: every matrix is
+        // skipped and gets NaN outputs (the workspace is never overrun).
+        for (int i = t; i < B; i += kPlanThreads) {
+            const int64_t ni = n[i];
+            if (cost[i] >= 0.0f) {
+                const double nan = __builtin_nan("");
+                for (int64_t q = 0; q < ni * ni; ++q) R[i][q] = nan;
+                double* cs = colsum != nullptr ? colsum[i] : nullptr;
+                if (cs != nullptr)
+                    for (int64_t q = 0; q < ni; ++q) cs[q] = nan;
+            }
+        }
+        __syncthreads();
+        for (int i = t; i < B; i += kPlanThreads) cost[i] = -1.0f;
+        __syncthreads();
     }
     // 4. offsets (exclusive scans over the ordered matrices) and descriptors
     int64_t it = 0, w = 0, k = 0;

@@ -73,11 +73,11 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     if (dt == TSNMF_F64) p.path = Path::F64;
     else p.path = (flags & TSNMF_LEAF_F64) ? Path::F32W : Path::F32;
     p.wide = n > 32;
-    p.waves = !p.wide ? 1 : (n <= 64 ? 2 : 4);
+    p.waves = !p.wide ? 1 : (n <= 64 ? 4 : 8);
     if (col) p.load = LOAD_COL;
     else if (ld == n && p.path != Path::F32W && !p.wide) p.load = LOAD_ROW_STAGED;
     else p.load = LOAD_ROW;
-    const int rpl = p.wide ? (p.path == Path::F32 ? 4 : 2)
+    const int rpl = p.wide ? (p.path == Path::F32 ? 8 : 4)
                            : (p.path == Path::F32 ? rows_per_lane_f32(n) : rows_per_lane_f64(n));
     p.block_rows = 64LL * rpl;
     if (cfg != nullptr && cfg->leaf_rows > 0) {
@@ -90,6 +90,8 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     // the ticket area bounds the number of leaves
     p.slab = std::max<int64_t>(p.slab, (m + kMaxLeaves - 1) / kMaxLeaves);
     p.streams = (m + p.slab - 1) / p.slab;
+    // the FP32 staged loads address a slab through a 32-bit byte range
+    if (p.load == LOAD_ROW_STAGED && p.path == Path::F32 && p.slab * n * 4 > kMaxBufSlabBytes) p.load = LOAD_ROW;
     return p;
 }
 

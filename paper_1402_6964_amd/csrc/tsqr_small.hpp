@@ -25,6 +25,10 @@
 namespace tsnmf {
 
 enum LoadKind : int { LOAD_ROW = 0, LOAD_ROW_STAGED = 1, LOAD_COL = 2 };
+// Largest slab (bytes) of the FP32 staged path, which addresses a slab
+// through one buffer resource with a 32-bit byte range.
+constexpr int64_t kMaxBufSlabBytes = ((int64_t)1 << 31) - 4096;
+
 struct StreamArgs {
     const void* X;         // input of element type TI, rows [0, m)
     int64_t m;             // rows
@@ -141,6 +145,37 @@ template <typename T, typename TI, int N, int RPL> struct Small {
         }
     }
 
+    // ---- staged load through a buffer resource -----------------------------------
+    // The resource covers the slab's rows only, and reads past its end return
+    // zero, so the block needs no per-element bounds masks.  `boff` is the
+    // block's byte offset within the slab.
+    static __device__ __forceinline__ void load_staged_buf(T (&x)[RPL][N], __amdgpu_buffer_rsrc_t rs, int boff,
+                                                           TI* St) {
+        static_assert(sizeof(T) == sizeof(TI) && sizeof(TI) == 4, "buffer staging is for FP32 input");
+        const int L = lane_id();
+        const int vo = boff + L * 4;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                const int e = (r * N + c) * 64;
+                x[r][c] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, e * 4, 2));
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                const int el = c * 64 + L;
+                St[(el / N) * SS + (el % N)] = (TI)x[r][c];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[r][c] = (T)St[L * SS + c];
+            wave_lds_sync();
+        }
+    }
+
     // ---- load one block of rows [b0, min(b0 + BR, r1)) ---------------------------
     template <int LOAD>
     static __device__ __forceinline__ void load(T (&x)[RPL][N], const StreamArgs& a, int64_t b0,
@@ -229,11 +264,31 @@ __device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, uns
     const int64_t r0 = sid * a.slab;
     const int64_t r1 = min(a.m, r0 + a.slab);
     double acc = 0.0;
-    for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
-        T x[RPL][N];
-        S::template load<LOAD>(x, a, b0, r1, St);
-        S::colsum_block(x, acc);
-        S::template step<0>(x, Rl);
+    constexpr bool kBuf = LOAD == LOAD_ROW_STAGED && sizeof(TI) == 4 && sizeof(T) == 4;
+    if constexpr (kBuf) {
+        // Buffer resource over this slab: base at row r0, range = the slab's
+        // bytes.  Callers keep slabs of this path below 2 GiB (kMaxBufSlabBytes).
+        // The slab index is wave-uniform; reading it through readfirstlane
+        // lets the compiler keep the resource in scalar registers (otherwise
+        // every load is wrapped in a loop over distinct lane values).
+        const int64_t r0u = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0 >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r0);
+        const int slab_bytes = __builtin_amdgcn_readfirstlane((int)((r1 - r0) * N * (int64_t)sizeof(TI)));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)((const TI*)a.X + r0u * N), 0, slab_bytes, 0x00020000);
+        for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
+            T x[RPL][N];
+            S::load_staged_buf(x, rs, (int)((b0 - r0) * N * (int64_t)sizeof(TI)), St);
+            S::colsum_block(x, acc);
+            S::template step<0>(x, Rl);
+        }
+    } else {
+        for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
+            T x[RPL][N];
+            S::template load<LOAD>(x, a, b0, r1, St);
+            S::colsum_block(x, acc);
+            S::template step<0>(x, Rl);
+        }
     }
     wave_lds_sync();
 

@@ -11,11 +11,15 @@ namespace tsnmf {
 
 // Rows per lane of one block: as many as the register file allows while the
 // block (RPL * n values per lane) and the step-0 partial sums stay resident.
+// For FP32 widths 17, 20, 26 and 28 the budget rule lands a few registers
+// above 256 (one wave per SIMD); they take the next smaller block.
 template <typename T, int N> constexpr int small_rpl() {
     constexpr int words = (int)(sizeof(T) / 4);
     constexpr int budget = words == 1 ? 168 : 64;  // block registers, in elements of T
     constexpr int r = budget / N;
-    return r >= 8 ? 8 : (r >= 6 ? 6 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)));
+    constexpr int rpl = r >= 8 ? 8 : (r >= 6 ? 6 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)));
+    constexpr bool tight = words == 1 && (N == 17 || N == 20 || N == 26 || N == 28);
+    return !tight ? rpl : (rpl == 8 ? 6 : 4);
 }
 
 template <typename T, typename TI, int N, int LOAD>

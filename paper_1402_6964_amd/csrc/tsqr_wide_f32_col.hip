@@ -3,7 +3,7 @@
 
 namespace tsnmf {
 hipError_t launch_wide_f32_col(const WideArgs& a, hipStream_t stream) {
-    if (a.n <= 64) return launch_wide_w<float, float, 2, LOAD_COL>(a, stream);
-    return launch_wide_w<float, float, 4, LOAD_COL>(a, stream);
+    if (a.n <= 64) return launch_wide_w<float, float, 4, LOAD_COL>(a, stream);
+    return launch_wide_w<float, float, 8, LOAD_COL>(a, stream);
 }
 }  // namespace tsnmf

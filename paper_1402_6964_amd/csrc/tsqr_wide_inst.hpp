@@ -8,11 +8,15 @@
 
 namespace tsnmf {
 
-template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 4 : 2; }
+// 16 columns per wave, W = 4 waves (up to 64 columns) or 8 (up to 128), and
+// as many rows per lane as 128 block registers hold: fewer columns per wave
+// mean a shorter butterfly per step and more rows to spread each step's fixed
+// cost (reflector scalars, pivot exchange, barrier) over.
+template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 8 : 4; }
 
 template <typename T, typename TI, int W, int LOAD>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
-    constexpr int NW = 32;
+    constexpr int NW = 16;
     constexpr int RPL = wide_rpl<T>();
     using S = Wide<T, TI, NW, W, RPL>;
     const size_t lds = S::lds_bytes();

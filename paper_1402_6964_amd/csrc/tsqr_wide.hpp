@@ -9,9 +9,11 @@
 // sigma = ||B(:, j)||^2 with one all-reduce, the dot products with its own
 // columns with one reduce-scatter butterfly, applies the reflector to its own
 // columns and keeps its own part of R(j, :) in LDS.  All waves use the same
-// sigma and alpha, so the reflector is identical in every wave.  The step
-// index runs in a loop (the pivot is read with a uniform register index), so
-// the code size does not grow with n.
+// sigma and alpha, so the reflector is identical in every wave.  Steps come
+// in rounds of W with the same local pivot column (Wide::level): the round
+// index is a compile-time constant, so the pivot is read straight from its
+// registers and the finished columns left of it drop out of the dot products
+// and updates.
 #pragma once
 #include "tsqr_small.hpp"
 
@@ -39,14 +41,88 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
     static constexpr int RW = NMAX * NW - W * NW * (NW - 1) / 2 + NMAX;   // FP64 slots per wave (bound)
     static constexpr size_t pv_elems() { return (size_t)2 * (RPL * 64 + 1); } // two pivot slots (T)
     static constexpr size_t lds_bytes() { return ((size_t)W * RW + 2) * 8 + pv_elems() * sizeof(T); }
-};
 
-template <int W> __device__ __forceinline__ int offw_me(const int (&offw)[W], int wv) {
-    int off = offw[0];
+    // The W steps j = Q W + o (o = 0 .. W-1) whose pivot is local column Q of
+    // wave o.  Q is a compile-time index, so the pivot is read straight from
+    // its registers and only local columns Q .. NW-1 take part: columns left of
+    // Q are finished in every wave.  Column Q itself is finished in waves
+    // wv < o (it was their pivot earlier in this round); it is still
+    // transformed there, harmlessly, and its R entries are not stored.
+    template <int Q>
+    static __device__ __forceinline__ void level(T (&x)[RPL][NW], int n, int wv, int L, double* Rw, double* apub,
+                                                 T* pv, int& off) {
+        if constexpr (Q < NW) {
+            constexpr int CNT = NW - Q;              // local columns Q .. NW-1
+            constexpr int V = pow2ceil(CNT);
+            constexpr int PV = ilog2(V);
+            if (Q * W >= n) return;
+            const int vi = bfly_vidx<PV>(L);         // this lane's value: local column Q + vi
+            for (int o = 0; o < W; ++o) {
+                const int j = Q * W + o;
+                if (j >= n) break;
+                const int c0 = Q + (wv < o ? 1 : 0); // first live local column of this wave
+                T* slot = pv + (j & 1) * (RPL * 64 + 1);
+                if (wv == o) {
 #pragma unroll
-    for (int u = 1; u < W; ++u) off = (u == wv) ? offw[u] : off;
-    return off;
-}
+                    for (int r = 0; r < RPL; ++r) slot[r * 64 + L] = x[r][Q];
+                    // R(j, j) is the first entry of the owner's row j; it is
+                    // overwritten in this step, so it is published before the barrier
+                    if (L == 0) apub[j & 1] = Rw[off];
+                }
+                __syncthreads();
+                T xp[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) xp[r] = slot[r * 64 + L];
+                const double alpha = apub[j & 1];
+                T sg = xp[0] * xp[0];
+#pragma unroll
+                for (int r = 1; r < RPL; ++r) sg = fma_t(xp[r], xp[r], sg);
+                const double sigma = (double)wave_sum(sg);
+                T p[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (v < CNT) {
+                        T d = xp[0] * x[0][Q + v];
+#pragma unroll
+                        for (int r = 1; r < RPL; ++r) d = fma_t(xp[r], x[r][Q + v], d);
+                        p[v] = d;
+                    } else {
+                        p[v] = T(0);
+                    }
+                }
+                const T D = butterfly<PV>(p);
+                const int c = Q + vi;
+                const bool mine = vi < CNT && c >= c0;
+                const bool piv = wv == o && vi == 0;
+                const double rj = mine ? Rw[off + c - c0] : 0.0;
+                const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
+                const bool live = sigma != 0.0;
+                const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+                const double inv_beta = rcp_fast<double>(beta);
+                const double s = live ? rcp_fast<double>(alpha - beta) : 0.0;
+                const double tau = live ? (beta - alpha) * inv_beta : 0.0;
+                const T cb = live ? (T)inv_beta : T(0);
+                double w = __builtin_fma(s, (double)D, rj);
+                if (piv) w = -beta;
+                double rn = __builtin_fma(-tau, w, rj);
+                if (piv) rn = beta;
+                if (mine) Rw[off + c - c0] = rn;
+                const T wt = (T)w;
+                T t[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) t[r] = cb * xp[r];
+#pragma unroll
+                for (int v = 0; v < CNT; ++v) {
+                    const T wk = lane_bcast(wt, bfly_lane(v, PV));
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) x[r][Q + v] = fma_t(t[r], wk, x[r][Q + v]);
+                }
+                off += NW - c0;
+            }
+            level<Q + 1>(x, n, wv, L, Rw, apub, pv, off);
+        }
+    }
+};
 
 // The W waves of the workgroup factor slab `sid` of `a` and store leaf node `sid`.
 template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
@@ -61,8 +137,6 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     T* pv = (T*)(apub + 2);
 
     for (int i = L; i < S::RW; i += 64) Rw[i] = 0.0;
-    const int vi = bfly_vidx<P>(L);                  // local column held by this lane after a butterfly
-    const int kcol = wv + W * vi;                    // its global column
 
     const int64_t r0 = sid * a.slab;
     const int64_t r1 = min(a.m, r0 + a.slab);
@@ -96,79 +170,8 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
             }
             acc += (double)butterfly<P>(p);
         }
-        int offw[W];                                 // start of row j in each wave's storage
-#pragma unroll
-        for (int u = 0; u < W; ++u) offw[u] = 0;
-        for (int j = 0; j < n; ++j) {
-            const int o = j % W;
-            const int q = j / W;
-            const int c0 = j > wv ? (j - wv + W - 1) / W : 0;   // first local column with k >= j
-            T* slot = pv + (j & 1) * (RPL * 64 + 1);
-            if (wv == o) {
-                // pivot column q of this wave, picked with uniform selects
-                // (a variable register index would move x to scratch memory)
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    T v = x[r][0];
-#pragma unroll
-                    for (int c = 1; c < NW; ++c) v = (c == q) ? x[r][c] : v;
-                    slot[r * 64 + L] = v;
-                }
-                // R(j, j) is the first entry of the owner's row j; it is
-                // overwritten in this step, so it is published before the barrier
-                if (L == 0) apub[j & 1] = Rw[offw_me(offw, wv)];
-            }
-            __syncthreads();
-            int off = offw[0];
-#pragma unroll
-            for (int u = 1; u < W; ++u) off = (u == wv) ? offw[u] : off;
-            T xp[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) xp[r] = slot[r * 64 + L];
-            const double alpha = apub[j & 1];        // R(j, j), published by the owner
-            T sg = xp[0] * xp[0];
-#pragma unroll
-            for (int r = 1; r < RPL; ++r) sg = fma_t(xp[r], xp[r], sg);
-            const double sigma = (double)wave_sum(sg);
-            T p[NW];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                T s = xp[0] * x[0][c];
-#pragma unroll
-                for (int r = 1; r < RPL; ++r) s = fma_t(xp[r], x[r][c], s);
-                p[c] = s;
-            }
-            const T D = butterfly<P>(p);
-            const bool mine = vi >= c0;              // this lane's column k satisfies k >= j
-            const double rj = mine ? Rw[off + vi - c0] : 0.0;
-            const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
-            const bool live = sigma != 0.0;
-            const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-            const double inv_beta = rcp_fast<double>(beta);
-            const double s = live ? rcp_fast<double>(alpha - beta) : 0.0;
-            const double tau = live ? (beta - alpha) * inv_beta : 0.0;
-            const T cb = live ? (T)inv_beta : T(0);
-            // Columns left of j are finished.  Their registers keep being
-            // transformed (harmlessly: their w only ever updates themselves),
-            // and their part of R is not written any more.
-            double w = __builtin_fma(s, (double)D, rj);
-            if (kcol == j) w = -beta;
-            double rn = __builtin_fma(-tau, w, rj);
-            if (kcol == j) rn = beta;
-            if (mine) Rw[off + vi - c0] = rn;
-            const T wt = (T)w;
-            T t[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) t[r] = cb * xp[r];
-#pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const T wk = lane_bcast(wt, bfly_lane(c, P));
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) x[r][c] = fma_t(t[r], wk, x[r][c]);
-            }
-#pragma unroll
-            for (int u = 0; u < W; ++u) offw[u] += NW - (j > u ? (j - u + W - 1) / W : 0);
-        }
+        int off = 0;                                 // start of row j in this wave's storage
+        Wide<T, TI, NW, W, RPL>::template level<0>(x, n, wv, L, Rw, apub, pv, off);
     }
     __syncthreads();
     // leaf node: row-major n x n FP64, zeros below the diagonal

@@ -12,8 +12,8 @@
 // the host side.
 //
 // Width classes: n = 16 and n = 32 with ld = n use the one-wave streaming
-// kernel (one slab per wave, four slabs per item); every other n <= 64, and
-// n <= 128, use the multi-wave kernel (four waves per slab).  Row blocks are
+// kernel (one slab per wave, eight slabs per item); every other n <= 64, and
+// n <= 128, use the multi-wave kernel (eight waves per slab).  Row blocks are
 // FP32, R is kept in FP64.  The reduction tree of each matrix runs inside the
 // same kernel: slabs are grouped, and the workgroup that completes the last
 // slab of a group (by ticket) factors the group's stacked R factors in FP64
@@ -33,26 +33,26 @@ namespace {
 
 enum : int { CLS_NONE = -1, CLS_S16 = 0, CLS_S32 = 1, CLS_W64 = 2, CLS_W128 = 3 };
 
-constexpr int kWaves = 4;                                   // waves per workgroup
+constexpr int kWaves = 8;                                   // waves per workgroup
 constexpr int kRplS16 = small_rpl<float, 16>();
 constexpr int kRplS32 = small_rpl<float, 32>();
-constexpr int kRplW64 = 8;        // 16 columns per wave
-constexpr int kRplW128 = 4;       // 32 columns per wave
-constexpr int kRplM64 = 4;        // FP64 merges, 16 columns per wave
-constexpr int kRplM128 = 2;       // FP64 merges, 32 columns per wave
+constexpr int kRplW64 = 16;       // 8 columns per wave
+constexpr int kRplW128 = 8;       // 16 columns per wave
+constexpr int kRplM64 = 8;        // FP64 merges, 8 columns per wave
+constexpr int kRplM128 = 4;       // FP64 merges, 16 columns per wave
 using S16 = Small<float, float, 16, kRplS16>;
 using S32 = Small<float, float, 32, kRplS32>;
-using W64 = Wide<float, float, 16, kWaves, kRplW64>;
-using W128 = Wide<float, float, 32, kWaves, kRplW128>;
-using M64 = Wide<double, double, 16, kWaves, kRplM64>;
-using M128 = Wide<double, double, 32, kWaves, kRplM128>;
+using W64 = Wide<float, float, 8, kWaves, kRplW64>;
+using W128 = Wide<float, float, 16, kWaves, kRplW128>;
+using M64 = Wide<double, double, 8, kWaves, kRplM64>;
+using M128 = Wide<double, double, 16, kWaves, kRplM128>;
 using C16 = CoopTree<16, kWaves>;
 using C32 = CoopTree<32, kWaves>;
 constexpr int kGroupW64 = 8;      // nodes per FP64 merge (n <= 64): <= 512 rows
 constexpr int kGroupW128 = 4;     // nodes per FP64 merge (n <= 128): <= 512 rows
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kLds = cmax(cmax(cmax(S16::lds_bytes(true), S32::lds_bytes(true)),
+constexpr size_t kLds = cmax(cmax(cmax(S16::lds_bytes(true, kWaves), S32::lds_bytes(true, kWaves)),
                                   cmax(W64::lds_bytes(), W128::lds_bytes())),
                              cmax(cmax(M64::lds_bytes(), M128::lds_bytes()),
                                   cmax(sizeof(CoopTreeLds<16, kWaves>), sizeof(CoopTreeLds<32, kWaves>))));
@@ -369,13 +369,13 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
         if (cls == CLS_S16 || cls == CLS_S32) {
             if (wv < ns) {
                 const StreamArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.tree};
-                if (cls == CLS_S16) small_slab<float, float, 16, kRplS16, LOAD_ROW_STAGED>(a, s0 + wv, smem, wv);
-                else small_slab<float, float, 32, kRplS32, LOAD_ROW_STAGED>(a, s0 + wv, smem, wv);
+                if (cls == CLS_S16) small_slab<float, float, 16, kRplS16, LOAD_ROW_STAGED, kWaves>(a, s0 + wv, smem, wv);
+                else small_slab<float, float, 32, kRplS32, LOAD_ROW_STAGED, kWaves>(a, s0 + wv, smem, wv);
             }
         } else {
             const WideArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.n, 0, M.tree};
-            if (cls == CLS_W64) wide_slab<float, float, 16, kWaves, kRplW64, LOAD_ROW>(a, s0, smem);
-            else wide_slab<float, float, 32, kWaves, kRplW128, LOAD_ROW>(a, s0, smem);
+            if (cls == CLS_W64) wide_slab<float, float, 8, kWaves, kRplW64, LOAD_ROW>(a, s0, smem);
+            else wide_slab<float, float, 16, kWaves, kRplW128, LOAD_ROW>(a, s0, smem);
         }
         // slab group ticket: every wave releases its node stores first
         grid_release();
@@ -393,8 +393,8 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
             grid_acquire();
             if (cls == CLS_S16) coop_tree_run<16, kWaves>(M.tree, g, *(CoopTreeLds<16, kWaves>*)smem);
             else if (cls == CLS_S32) coop_tree_run<32, kWaves>(M.tree, g, *(CoopTreeLds<32, kWaves>*)smem);
-            else if (cls == CLS_W64) wide_merge_run<16, kRplM64, kGroupW64>(M.tree, M.n, g, smem, &go_sh);
-            else wide_merge_run<32, kRplM128, kGroupW128>(M.tree, M.n, g, smem, &go_sh);
+            else if (cls == CLS_W64) wide_merge_run<8, kRplM64, kGroupW64>(M.tree, M.n, g, smem, &go_sh);
+            else wide_merge_run<16, kRplM128, kGroupW128>(M.tree, M.n, g, smem, &go_sh);
         }
         __syncthreads();     // LDS is reused by the next item
     }

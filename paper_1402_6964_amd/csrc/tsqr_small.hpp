@@ -74,10 +74,12 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     static constexpr int RS = roff(N);                    // R slots per wave (elements of T)
     static constexpr int SS = (N % 2) ? N : N + 1;        // staging row stride, odd -> no bank conflicts
     static constexpr int STG = 64 * SS;                   // staging elements (TI) per wave
-    static constexpr size_t r_bytes() { return (size_t)4 * RS * sizeof(TR); }
-    static constexpr size_t stage_off() { return (r_bytes() + 15) & ~(size_t)15; }
-    static constexpr size_t lds_bytes(bool staged) {  // per workgroup of 4 waves
-        return stage_off() + (staged ? (size_t)4 * STG * sizeof(TI) : 0);
+    // LDS of a workgroup of `wpg` waves: every wave's R, then every wave's
+    // staging area
+    static constexpr size_t r_bytes(int wpg = 4) { return (size_t)wpg * RS * sizeof(TR); }
+    static constexpr size_t stage_off(int wpg = 4) { return (r_bytes(wpg) + 15) & ~(size_t)15; }
+    static constexpr size_t lds_bytes(bool staged, int wpg = 4) {
+        return stage_off(wpg) + (staged ? (size_t)wpg * STG * sizeof(TI) : 0);
     }
 
     // ---- one Householder step (column J) -------------------------------------
@@ -250,13 +252,14 @@ template <typename T, typename TI, int N, int RPL> struct Small {
 };
 
 // One wave factors slab `sid` of `a` and stores leaf node `sid`.  `smem` is the
-// workgroup's LDS laid out as in Small::lds_bytes, `wv` the wave's slot in it.
-template <typename T, typename TI, int N, int RPL, int LOAD>
+// workgroup's LDS laid out as in Small::lds_bytes for WPG waves, `wv` the
+// wave's slot in it.
+template <typename T, typename TI, int N, int RPL, int LOAD, int WPG = 4>
 __device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, unsigned char* smem, int wv) {
     using S = Small<T, TI, N, RPL>;
     const int L = lane_id();
     double* Rl = (double*)smem + wv * S::RS;
-    TI* St = (TI*)(smem + S::stage_off()) + wv * S::STG;
+    TI* St = (TI*)(smem + S::stage_off(WPG)) + wv * S::STG;
 
     for (int i = L; i < S::RS; i += 64) Rl[i] = 0.0;
     wave_lds_sync();

@@ -98,7 +98,10 @@ int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags
 typedef struct tsnmf_tsqr_config {
     int64_t leaf_rows;      /* rows per workgroup slab (the TSQR leaf); rounded up
                                to a whole number of row blocks                    */
-    int32_t tree_arity;     /* slab factors merged per tree node: 0 or 2 (binary) */
+    int32_t tree_arity;     /* slab factors merged per tree node, 2..64 (2 = a
+                               binary tree); n <= 32 only, capped at the most
+                               stacked rows one workgroup pass holds; the wider
+                               paths use a binary tree.  0 = library default. */
     int32_t rows_per_lane;  /* row block height = 64 * rows_per_lane; 1..8        */
 } tsnmf_tsqr_config;
 

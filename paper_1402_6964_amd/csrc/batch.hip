@@ -72,8 +72,14 @@ __host__ __device__ constexpr int64_t class_block(int c) {
 __host__ __device__ constexpr int64_t class_slab(int c) {
     return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4096 : c == CLS_W64 ? 8192 : 16384;
 }
+// Nodes per tree group.  For the one-wave classes a group must hold whole
+// items (multiples of kWaves slabs); 24 and 16 are near the fastest pass sizes.
+constexpr int kGroupS16 = 24;
+constexpr int kGroupS32 = 16;
+static_assert(kGroupS16 % kWaves == 0 && kGroupS32 % kWaves == 0, "groups hold whole items");
+static_assert(kGroupS16 <= C16::G && kGroupS32 <= C32::G, "groups fit one pass");
 __host__ __device__ constexpr int64_t class_group(int c) {
-    return c == CLS_S16 ? C16::G : c == CLS_S32 ? C32::G : c == CLS_W64 ? kGroupW64 : kGroupW128;
+    return c == CLS_S16 ? kGroupS16 : c == CLS_S32 ? kGroupS32 : c == CLS_W64 ? kGroupW64 : kGroupW128;
 }
 __host__ __device__ constexpr int class_per_item(int c) { return (c == CLS_S16 || c == CLS_S32) ? kWaves : 1; }
 
@@ -251,6 +257,7 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
             const int64_t nodes = s.words / (n[i] * n[i] + n[i]);
             d.tree.node_cs = words + wo + nodes * n[i] * n[i];
             d.tree.leaves = s.leaves;
+            d.tree.group = (int32_t)d.group;
             d.tree.R = R[i];
             d.tree.colsum = colsum != nullptr ? colsum[i] : nullptr;
             ito += s.items;

@@ -133,6 +133,7 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
     tree.leaves = p.streams;
     tree.R = R;
     tree.colsum = colsum;
+    tree.group = cfg != nullptr && cfg->tree_arity > 0 ? cfg->tree_arity : 0;
     StreamArgs a{};
     a.X = X;
     a.m = m;

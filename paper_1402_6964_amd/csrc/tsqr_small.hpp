@@ -336,15 +336,6 @@ template <int N, int W_ = 8> struct CoopTree {
     static constexpr int G = CAP / N < 64 ? CAP / N : 64;   // nodes per pass
 };
 
-template <int N> constexpr int64_t coop_tree_nodes(int64_t leaves) {
-    int64_t total = 0, c = leaves;
-    while (c > 1) {
-        total += c;
-        c = (c + CoopTree<N>::G - 1) / CoopTree<N>::G;
-    }
-    return total + 1;
-}
-
 template <int N, int W = 8> struct CoopTreeLds {
     double sR[W][Small<double, double, N, CoopTree<N, W>::RPL>::RS];
     double xchg[2 * W * 64];
@@ -352,11 +343,46 @@ template <int N, int W = 8> struct CoopTreeLds {
 };
 
 // The whole workgroup (W waves) reduces group `group0` of level 0 and climbs.
+// Nodes per group: t.group when set (2 .. CT::G), else a default by width.
+// A pass costs about the same per stacked row whatever the group size, but
+// it runs on one workgroup, so smaller groups spread the first level over
+// more workgroups; measured on 2048 slab factors, 16 nodes per pass (20 for
+// 10..19 columns) beat the full 1024-row pass (n = 25: 88 against 132 us).
+template <int N, int W = 8> __host__ __device__ constexpr int coop_group(int group) {
+    constexpr int cap = CoopTree<N, W>::G;
+    constexpr int dflt = N >= 20 ? 16 : (N >= 10 ? 20 : cap);
+    const int g = group == 0 ? dflt : group;
+    return g >= 2 && g < cap ? g : cap;
+}
+
+// Factor `rows` stacked FP64 rows at `src` (n wide) with WA of the W waves
+// (WA = the fewest that hold them, a power of two): idle waves only match the
+// per-step barriers, so a small group runs at the speed of a small workgroup.
+template <int N, int W, int WA>
+__device__ __forceinline__ void coop_factor(const double* src, int rows, double* Rl, double* xchg, int wv, int L) {
+    using CT = CoopTree<N, W>;
+    using S = Small<double, double, N, CT::RPL>;
+    if (wv < WA) {
+        double x[CT::RPL][N];
+#pragma unroll
+        for (int r = 0; r < CT::RPL; ++r) {
+            const int b = wv * (64 * CT::RPL) + r * 64 + L;
+            const bool ok = b < rows;
+            const double* rowp = src + (int64_t)min(b, rows - 1) * N;
+#pragma unroll
+            for (int c = 0; c < N; ++c) x[r][c] = ok ? rowp[c] : 0.0;
+        }
+        S::template step<0, WA>(x, Rl, xchg);
+    } else if constexpr (WA > 1) {
+        for (int j = 0; j < N; ++j) __syncthreads();   // one barrier per step of the active waves
+    }
+}
+
 template <int N, int W = 8>
 __device__ __forceinline__ void coop_tree_run(const TreeArgs& t, int64_t group0, CoopTreeLds<N, W>& lds) {
     using CT = CoopTree<N, W>;
     using S = Small<double, double, N, CT::RPL>;
-    constexpr int G = CT::G;
+    const int G = coop_group<N, W>(t.group);
     constexpr int64_t NN = (int64_t)N * N;
     double* xchg = lds.xchg;
     int& go = lds.go;
@@ -373,17 +399,12 @@ __device__ __forceinline__ void coop_tree_run(const TreeArgs& t, int64_t group0,
         const int rows = (int)min((int64_t)G, count - first) * N;
         for (int i = L; i < S::RS; i += 64) Rl[i] = 0.0;
         wave_lds_sync();
-        double x[CT::RPL][N];
         const double* src = t.nodes + (base + first) * NN;    // stacked rows, n wide
-#pragma unroll
-        for (int r = 0; r < CT::RPL; ++r) {
-            const int b = wv * (64 * CT::RPL) + r * 64 + L;
-            const bool ok = b < rows;
-            const double* rowp = src + (int64_t)min(b, rows - 1) * N;
-#pragma unroll
-            for (int c = 0; c < N; ++c) x[r][c] = ok ? rowp[c] : 0.0;
-        }
-        S::template step<0, CT::W>(x, Rl, xchg);
+        const int need = (rows + 64 * CT::RPL - 1) / (64 * CT::RPL);
+        if (need <= 1) coop_factor<N, W, 1>(src, rows, Rl, xchg, wv, L);
+        else if (W >= 2 && need <= 2) coop_factor<N, W, (W >= 2 ? 2 : 1)>(src, rows, Rl, xchg, wv, L);
+        else if (W >= 4 && need <= 4) coop_factor<N, W, (W >= 4 ? 4 : 1)>(src, rows, Rl, xchg, wv, L);
+        else coop_factor<N, W, W>(src, rows, Rl, xchg, wv, L);
         wave_lds_sync();
         double cs = 0.0;
         if (wv == 0 && L < N) {

@@ -22,6 +22,9 @@ template <typename T, int N> constexpr int small_rpl() {
     return !tight ? rpl : (rpl == 8 ? 6 : 4);
 }
 
+// One workgroup per group of leaves; later levels by ticket (tsqr_coop_tree.hip).
+hipError_t launch_coop_tree(int n, const TreeArgs& t, hipStream_t stream);
+
 template <typename T, typename TI, int N, int LOAD>
 hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
     constexpr int RPL = small_rpl<T, N>();
@@ -37,12 +40,9 @@ hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     profile_split(stream);
-    // reduction tree: one workgroup per group of G leaves, later levels by ticket
-    constexpr int G = CoopTree<N>::G;
-    const int64_t groups = (a.tree.leaves + G - 1) / G;
-    hipLaunchKernelGGL(tsqr_coop_tree_kernel<N>, dim3((unsigned)groups), dim3(CoopTree<N>::W * 64), 0, stream,
-                       a.tree);
-    return hipGetLastError();
+    // reduction tree (FP64 whatever the leaf type; its kernels live in one
+    // translation unit)
+    return launch_coop_tree(N, a.tree, stream);
 }
 
 #define TSNMF_SMALL_CASE(N) \

@@ -20,6 +20,8 @@ struct TreeArgs {
     int64_t leaves;      // nodes at level 0
     double* R;           // final R, n x n column-major
     double* colsum;      // final column sums or nullptr
+    int32_t group;       // nodes per tree group (n <= 32 trees); 0 = the default
+    int32_t pad_;
 };
 
 __device__ __forceinline__ void grid_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }

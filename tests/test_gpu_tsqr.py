@@ -120,7 +120,8 @@ def test_configs_give_the_same_r(lib):
     """Tree invariance on the GPU: leaf heights / arities change only rounding."""
     X = synth.random_matrix(123_457, 12, dtype=torch.float32, seed_tag=6).cuda()
     R0, _ = _run(lib, X)
-    for leaf, arity in [(256, 2), (1000, 0), (5000, 2), (64, 2), (123_457, 2)]:
+    for leaf, arity in [(256, 2), (1000, 0), (5000, 2), (64, 2), (123_457, 2), (256, 3), (512, 7),
+                        (256, 64), (1000, 16)]:
         cfg = lib.TsqrConfig(leaf_rows=leaf, tree_arity=arity, rows_per_lane=0)
         R1, _ = _run(lib, X, config=cfg)
         assert np.abs(R1 - R0).max() / np.abs(R0).max() <= 1e-5
@@ -188,8 +189,9 @@ def test_invalid_arguments(lib):
     assert lib.tsnmf_tsqr_r(X, 10, 4, 4, lib.BF16, R) == -5
     assert lib.tsnmf_tsqr_r(X, 10, 4, 4, lib.F32, None) == -6
     assert lib.tsnmf_tsqr_r(X, 10, 300, 300, lib.F32, R) == 4
-    bad = lib.TsqrConfig(leaf_rows=0, tree_arity=3, rows_per_lane=0)
-    assert lib.tsnmf_tsqr_r_ex(X, 10, 4, 4, lib.F32, R, None, bad) == -8
+    for arity in (1, 65, -2):
+        bad = lib.TsqrConfig(leaf_rows=0, tree_arity=arity, rows_per_lane=0)
+        assert lib.tsnmf_tsqr_r_ex(X, 10, 4, 4, lib.F32, R, None, bad) == -8
 
 
 # ---- wide factors (33..128 columns) ------------------------------------------------
@@ -253,3 +255,16 @@ def test_heat_transfer_tiled_full_size(lib):
     assert np.max(np.abs(np.linalg.norm(Rg, axis=0) - cn) / cn) <= 1e-5
     dA = np.abs(Ah).sum(0)
     assert np.max(np.abs(csg - t * dA) / (t * dA)) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 16, 25, 32])
+def test_tree_group_sizes_match_oracle(lib, n):
+    """Every tree group size (2 .. 64 nodes per pass, capped by the pass
+    capacity), with passes that use 1, 2, 4 or all 8 waves, against the oracle."""
+    X = synth.random_matrix(400_003, n, dtype=torch.float32, seed_tag=60 + n, dist="uniform")
+    Xh = X.numpy()
+    Xd = X.cuda()
+    for arity in (2, 3, 5, 8, 13, 40, 64):
+        cfg = lib.TsqrConfig(leaf_rows=1024, tree_arity=arity, rows_per_lane=0)
+        Rg, csg = _run(lib, Xd, config=cfg)
+        _check_against_oracle(Rg, csg, Xh, 1e-6, 2e-5, 1e-6, norm_tol=1e-5)

@@ -102,7 +102,8 @@ typedef struct tsnmf_tsqr_config {
                                binary tree); n <= 32 only, capped at the most
                                stacked rows one workgroup pass holds; the wider
                                paths use a binary tree.  0 = library default. */
-    int32_t rows_per_lane;  /* row block height = 64 * rows_per_lane; 1..8        */
+    int32_t rows_per_lane;  /* reserved, must be 0: the row block height is fixed
+                               per width when the library is compiled        */
 } tsnmf_tsqr_config;
 
 /* As tsnmf_tsqr_r with an explicit configuration (`cfg` is a host pointer or

@@ -147,7 +147,7 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
     if (R == nullptr) return -6;
     if (cfg != nullptr) {
         if (cfg->leaf_rows < 0 || (cfg->tree_arity != 0 && (cfg->tree_arity < 2 || cfg->tree_arity > 64)) ||
-            cfg->rows_per_lane < 0 || cfg->rows_per_lane > 8)
+            cfg->rows_per_lane != 0)
             return -8;
     }
     if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;

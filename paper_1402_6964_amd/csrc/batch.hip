@@ -34,8 +34,8 @@ namespace {
 enum : int { CLS_NONE = -1, CLS_S16 = 0, CLS_S32 = 1, CLS_W64 = 2, CLS_W128 = 3 };
 
 constexpr int kWaves = 8;                                   // waves per workgroup
-constexpr int kRplS16 = small_rpl<float, 16>();
-constexpr int kRplS32 = small_rpl<float, 32>();
+constexpr int kRplS16 = 8;        // one-wave classes: 512- and 256-row blocks
+constexpr int kRplS32 = 4;
 constexpr int kRplW64 = 16;       // 8 columns per wave
 constexpr int kRplW128 = 8;       // 16 columns per wave
 constexpr int kRplM64 = 8;        // FP64 merges, 8 columns per wave

@@ -21,8 +21,8 @@ hipError_t launch_wide_f64_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f64_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_col(const WideArgs& a, hipStream_t s);
-int rows_per_lane_f32(int n);
-int rows_per_lane_f64(int n);
+int rows_per_lane_f32(int n, bool staged);
+int rows_per_lane_f64(int n, bool staged);
 
 namespace {
 
@@ -78,7 +78,8 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     else if (ld == n && p.path != Path::F32W && !p.wide) p.load = LOAD_ROW_STAGED;
     else p.load = LOAD_ROW;
     const int rpl = p.wide ? (p.path == Path::F32 ? 8 : 4)
-                           : (p.path == Path::F32 ? rows_per_lane_f32(n) : rows_per_lane_f64(n));
+                           : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
+                                                  : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
     p.block_rows = 64LL * rpl;
     if (cfg != nullptr && cfg->leaf_rows > 0) {
         p.slab = cfg->leaf_rows;

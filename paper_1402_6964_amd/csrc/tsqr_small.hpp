@@ -106,7 +106,7 @@ template <typename T, typename TI, int N, int RPL> struct Small {
                     p[v] = T(0);
                 }
             }
-            T D = butterfly<P>(p);                   // lane L: d_{J + vidx(L)}
+            T D = butterfly<P, CNT>(p);              // lane L: d_{J + vidx(L)}
             if constexpr (W > 1) {
                 const int wv = (int)(threadIdx.x >> 6);
                 T* xb = xchg + (J & 1) * (W * 64);   // alternate buffers: one barrier per step
@@ -247,7 +247,7 @@ template <typename T, typename TI, int N, int RPL> struct Small {
                 p[c] = T(0);
             }
         }
-        acc += (double)butterfly<PN>(p);
+        acc += (double)butterfly<PN, N>(p);
     }
 };
 

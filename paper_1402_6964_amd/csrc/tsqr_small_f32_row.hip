@@ -11,11 +11,11 @@ hipError_t launch_small_f32_row(int n, const StreamArgs& a, hipStream_t stream) 
 }  // namespace tsnmf
 
 namespace tsnmf {
-int rows_per_lane_f32(int n) {
+int rows_per_lane_f32(int n, bool staged) {
     using T_ = float;
     TSNMF_SMALL_RPL_SWITCH
 }
-int rows_per_lane_f64(int n) {
+int rows_per_lane_f64(int n, bool staged) {
     using T_ = double;
     TSNMF_SMALL_RPL_SWITCH
 }

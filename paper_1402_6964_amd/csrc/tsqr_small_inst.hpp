@@ -9,17 +9,28 @@
 
 namespace tsnmf {
 
-// Rows per lane of one block: as many as the register file allows while the
-// block (RPL * n values per lane) and the step-0 partial sums stay resident.
-// For FP32 widths 17, 20, 26 and 28 the budget rule lands a few registers
-// above 256 (one wave per SIMD); they take the next smaller block.
-template <typename T, int N> constexpr int small_rpl() {
-    constexpr int words = (int)(sizeof(T) / 4);
-    constexpr int budget = words == 1 ? 168 : 64;  // block registers, in elements of T
-    constexpr int r = budget / N;
-    constexpr int rpl = r >= 8 ? 8 : (r >= 6 ? 6 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)));
-    constexpr bool tight = words == 1 && (N == 17 || N == 20 || N == 26 || N == 28);
-    return !tight ? rpl : (rpl == 8 ? 6 : 4);
+// Rows per lane of one block: as many as fit beside the block's partial sums
+// in 256 registers (two waves per SIMD).  FP32 widths 9..32 take the largest
+// value that the compiler fits without accumulation registers or spills
+// (measured per width; the allocation does not grow monotonically with the
+// block); other widths follow a register budget.
+constexpr int kRplF32[33] = {8, 8, 8, 8, 8, 8, 8, 8, 8,            // 0..8
+                             11, 11, 11, 10, 9, 11, 11, 10,       // 9..16
+                             9, 8, 8, 7, 7, 7, 7, 6,              // 17..24
+                             6, 5, 6, 5, 5, 5, 5, 5};             // 25..32
+// Direct (unstaged) loads keep more addresses live: smaller blocks from 23
+// columns on.
+constexpr int kRplF32Direct[33] = {8, 8, 8, 8, 8, 8, 8, 8, 8,      // 0..8
+                                   11, 11, 11, 10, 9, 11, 11, 10, // 9..16
+                                   9, 8, 8, 7, 7, 7, 6, 6,        // 17..24
+                                   5, 5, 5, 4, 4, 4, 4, 4};       // 25..32
+template <typename T, int N, int LOAD = LOAD_ROW_STAGED> constexpr int small_rpl() {
+    if constexpr (sizeof(T) == 4) {
+        return LOAD == LOAD_ROW_STAGED ? kRplF32[N] : kRplF32Direct[N];
+    } else {
+        constexpr int r = 64 / N;                      // FP64: 64 block registers' worth of elements
+        return r >= 8 ? 8 : (r >= 6 ? 6 : (r >= 4 ? 4 : (r >= 2 ? 2 : 1)));
+    }
 }
 
 // One workgroup per group of leaves; later levels by ticket (tsqr_coop_tree.hip).
@@ -27,7 +38,7 @@ hipError_t launch_coop_tree(int n, const TreeArgs& t, hipStream_t stream);
 
 template <typename T, typename TI, int N, int LOAD>
 hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
-    constexpr int RPL = small_rpl<T, N>();
+    constexpr int RPL = small_rpl<T, N, LOAD>();
     using S = Small<T, TI, N, RPL>;
     const size_t lds = S::lds_bytes(LOAD == LOAD_ROW_STAGED);
     auto kern = tsqr_small_kernel<T, TI, N, RPL, LOAD>;
@@ -62,7 +73,7 @@ hipError_t launch_small_n(const StreamArgs& a, hipStream_t stream) {
     }
 
 #define TSNMF_SMALL_RPL_CASE(N) \
-    case N: return small_rpl<T_, N>();
+    case N: return staged ? small_rpl<T_, N, LOAD_ROW_STAGED>() : small_rpl<T_, N, LOAD_ROW>();
 
 #define TSNMF_SMALL_RPL_SWITCH                                                                   \
     switch (n) {                                                                                 \

@@ -90,7 +90,7 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                         p[v] = T(0);
                     }
                 }
-                const T D = butterfly<PV>(p);
+                const T D = butterfly<PV, CNT>(p);
                 const int c = Q + vi;
                 const bool mine = vi < CNT && c >= c0;
                 const bool piv = wv == o && vi == 0;

@@ -119,29 +119,32 @@ __host__ __device__ constexpr __forceinline__ int pow2ceil(int v) {
 
 // One stage over the live values p[0 .. 2^(P - S) - 1]: S is the stage index
 // (0 = bit 5).  Pairs (p[2i], p[2i+1]) -> p[i] while values remain, then
-// all-reduce.
-template <int P, int S, typename T> __device__ __forceinline__ void bfly_stage(T* p) {
+// all-reduce.  Values at index >= LIVE are known to be zero (padding up to a
+// power of two): a pair of two such values stays zero without instructions.
+template <int P, int S, int LIVE, typename T> __device__ __forceinline__ void bfly_stage(T* p) {
     constexpr int BIT = 5 - S;
     if constexpr (S < P) {
         constexpr int HALF = 1 << (P - S - 1);
 #pragma unroll
-        for (int i = 0; i < HALF; ++i) p[i] = pair_stage<BIT>(p[2 * i], p[2 * i + 1]);
+        for (int i = 0; i < HALF; ++i) p[i] = 2 * i < LIVE ? pair_stage<BIT>(p[2 * i], p[2 * i + 1]) : T(0);
     } else {
         p[0] = allreduce_stage<BIT>(p[0]);
     }
 }
 
-// Reduce-scatter of V = 2^P values (P <= 5) held in p[0..V-1] (clobbered).
-// Returns the register whose lane L holds the wave-wide sum of value
-// bfly_vidx<P>(L).
-template <int P, typename T> __device__ __forceinline__ T butterfly(T* p) {
+// Reduce-scatter of V = 2^P values (P <= 5) held in p[0..V-1] (clobbered),
+// of which the first LIVE may be nonzero.  Returns the register whose lane L
+// holds the wave-wide sum of value bfly_vidx<P>(L).
+template <int P, int LIVE = (1 << P), typename T> __device__ __forceinline__ T butterfly(T* p) {
     static_assert(P >= 0 && P <= 5, "at most 32 values per butterfly");
-    bfly_stage<P, 0>(p);
-    bfly_stage<P, 1>(p);
-    bfly_stage<P, 2>(p);
-    bfly_stage<P, 3>(p);
-    bfly_stage<P, 4>(p);
-    bfly_stage<P, 5>(p);
+    static_assert(LIVE >= 1 && LIVE <= (1 << P), "live values within the butterfly");
+    constexpr int L1 = (LIVE + 1) / 2, L2 = (L1 + 1) / 2, L3 = (L2 + 1) / 2, L4 = (L3 + 1) / 2;
+    bfly_stage<P, 0, LIVE>(p);
+    bfly_stage<P, 1, L1>(p);
+    bfly_stage<P, 2, L2>(p);
+    bfly_stage<P, 3, L3>(p);
+    bfly_stage<P, 4, L4>(p);
+    bfly_stage<P, 5, 1>(p);
     return p[0];
 }
 

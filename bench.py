@@ -251,8 +251,12 @@ def extras(torch, tsnmf, synth, dev, check=True):
         t = _timed(torch, gp, 3)
         tf = 2.0 * m * n * k / t / 1e12
         proj[name] = {"ms": round(t * 1e3, 3), "tflops": round(tf, 1), "peak_tflops": peak,
-                      "frac": round(tf / peak, 4), "gbs": round(Xin.numel() * Xin.element_size() / t / 1e9, 1)}
-    out["projection"] = {"workload": "20,000,000 x 128, k = 512", **proj}
+                      "frac": round(tf / peak, 4), "gbs": round(Xin.numel() * Xin.element_size() / t / 1e9, 1),
+                      "gnormals_per_s": round(m * k / t / 1e9, 1)}
+    # each Gaussian feeds 2 n = 256 flops, so the matrix cores need 4 normals
+    # per SIMD per clock; Philox-10 + Box-Muller on the vector units makes the
+    # generation, not the MFMA, the bound of the BF16 path
+    out["projection"] = {"workload": "20,000,000 x 128, k = 512", "gaussians": m * k, **proj}
     del X, Xb, d, Y
     torch.cuda.empty_cache()
 

@@ -290,71 +290,6 @@ __device__ __forceinline__ int find_matrix(const int64_t* prefix, int cnt, int64
     return lo;
 }
 
-// FP64 G-ary tree for the wide classes: a group of up to G stacked n x n nodes
-// (row-major, so the group is a (G n) x n row-major matrix) is factored by the
-// wide streaming kernel in FP64 into one node of the next level.
-template <int NW, int RPLD, int G>
-__device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t group0, unsigned char* smem, int* go) {
-    const int tid = (int)threadIdx.x;
-    const int64_t nn = (int64_t)n * n;
-    int64_t group = group0, count = t.leaves, base = 0, tbase = 0;
-    while (true) {
-        const int64_t first = group * G;
-        const int cnt = (int)min((int64_t)G, count - first);
-        const int64_t nbase = base + count;
-        const int64_t ncount = (count + G - 1) / G;
-        WideArgs a{};
-        a.X = t.nodes + (base + first) * nn;
-        a.m = (int64_t)cnt * n;
-        a.ld = n;
-        a.slab = a.m;
-        a.nstreams = 1;
-        a.n = n;
-        a.tree = t;
-        a.tree.nodes = t.nodes + (nbase + group) * nn;
-        a.tree.node_cs = nullptr;
-        wide_slab<double, double, NW, kWaves, RPLD, LOAD_ROW>(a, 0, smem);
-        double* cs_out = t.node_cs + (nbase + group) * n;
-        for (int c = tid; c < n; c += kWaves * 64) {
-            double s = 0.0;
-            for (int q = 0; q < cnt; ++q) s += t.node_cs[(base + first + q) * n + c];
-            cs_out[c] = s;
-        }
-        __syncthreads();
-        if (ncount == 1) {
-            // top: R column-major with rows flipped to a nonnegative diagonal
-            const double* top = t.nodes + (nbase + group) * nn;
-            for (int i = tid; i < n * n; i += kWaves * 64) {
-                const int r = i % n, c = i / n;
-                const double d = top[(int64_t)r * n + r];
-                const double v = top[(int64_t)r * n + c];
-                t.R[i] = c >= r ? (d < 0.0 ? -v : v) : 0.0;
-            }
-            if (t.colsum != nullptr)
-                for (int c = tid; c < n; c += kWaves * 64) t.colsum[c] = cs_out[c];
-            return;
-        }
-        grid_release();
-        __syncthreads();
-        const int64_t ngroup = group / G;
-        const int gsize = (int)min((int64_t)G, ncount - ngroup * G);
-        if (tid == 0) {
-            const int old = __hip_atomic_fetch_add(t.tickets + tbase + ngroup, 1, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            const int last = old == gsize - 1;
-            if (last) __hip_atomic_store(t.tickets + tbase + ngroup, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            *go = last;
-        }
-        __syncthreads();
-        if (!*go) return;
-        grid_acquire();
-        tbase += (ncount + G - 1) / G;
-        base = nbase;
-        count = ncount;
-        group = ngroup;
-    }
-}
-
 __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const BatchMat* __restrict__ mats,
                                                             const int64_t* __restrict__ iprefix, int B) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -400,8 +335,8 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
             grid_acquire();
             if (cls == CLS_S16) coop_tree_run<16, kWaves>(M.tree, g, *(CoopTreeLds<16, kWaves>*)smem);
             else if (cls == CLS_S32) coop_tree_run<32, kWaves>(M.tree, g, *(CoopTreeLds<32, kWaves>*)smem);
-            else if (cls == CLS_W64) wide_merge_run<8, kRplM64, kGroupW64>(M.tree, M.n, g, smem, &go_sh);
-            else wide_merge_run<16, kRplM128, kGroupW128>(M.tree, M.n, g, smem, &go_sh);
+            else if (cls == CLS_W64) wide_merge_run<8, kWaves, kRplM64, kGroupW64>(M.tree, M.n, g, smem, &go_sh);
+            else wide_merge_run<16, kWaves, kRplM128, kGroupW128>(M.tree, M.n, g, smem, &go_sh);
         }
         __syncthreads();     // LDS is reused by the next item
     }

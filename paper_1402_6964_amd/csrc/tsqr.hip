@@ -98,13 +98,16 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Node storage of a tree over `leaves` factors: the levels of a binary tree
+// bound those of any group size, plus the top node (which the wide tree
+// stores above a single leaf too).
 int64_t tree_nodes(int64_t leaves) {
     int64_t total = 0, c = leaves;
     while (c > 1) {
         total += c;
         c = (c + 1) / 2;
     }
-    return total + 1;
+    return total + 2;
 }
 
 size_t plan_bytes(const Plan& p, int n) {

@@ -197,176 +197,85 @@ __global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
     wide_slab<T, TI, NW, W, RPL, LOAD>(a, blockIdx.x, smem);
 }
 
-}  // namespace tsnmf
-
-namespace tsnmf {
-
-// ---- FP64 tree for wide factors ------------------------------------------------
+// ---- FP64 G-ary tree for wide factors -------------------------------------------
 //
-// Binary tree over the leaf nodes; a workgroup of W waves merges one pair
-// (QR of [A; B], both upper triangular n x n) and climbs by ticket.  Column k
-// belongs to a group of QL = 64 W / NMAX lanes; lane g of the group holds rows
-// g, g + QL, ... of column k of A and of B.  At step j the group of column j
-// stores B(:, j) and A(j, j) in LDS; after a block barrier every lane reads the
-// entries of its own rows, forms partial sums of ||B(:, j)||^2 and of
-// B(:, j)^T B(:, k) over those rows, and the group adds them (DPP within the
-// quad), so every group holds the same sigma.  The lane holding A(j, k)
-// computes w_k = A(j, k) + dot_k / (alpha - beta), shares it with its group,
-// and the group updates its rows of B(:, k).  B(i, j) = 0 for i > j, so the
-// full-length sums are exact without masking.
-template <int NMAX, int W> struct TTWide {
-    static constexpr int QL = 64 * W / NMAX;     // lanes per column
-    static constexpr int RL = NMAX / QL;          // rows per lane
-    static_assert(QL == 4 || QL == 8, "four or eight lanes per column");
-};
-
-// Sum over aligned groups of QL lanes (every lane of the group gets it).
-template <int QL> __device__ __forceinline__ double group_sum(double x) {
-    x += dpp_read<kDppXor1>(x);
-    x += dpp_read<kDppXor2>(x);
-    if constexpr (QL == 8) x += dpp_read<kDppRowHalfMirror>(x);
-    return x;
-}
-
-template <int NMAX> struct WideTreeLds {
-    double sy[NMAX + 1];
-    int go;
-};
-
-// The workgroup merges pair `pair0` of level 0 and climbs.
-template <int NMAX, int W>
-__device__ __forceinline__ void wide_tree_run(const TreeArgs& t, int n, int64_t pair0, WideTreeLds<NMAX>& lds) {
-    using TT = TTWide<NMAX, W>;
-    constexpr int QL = TT::QL, RL = TT::RL;
-    double* sy = lds.sy;
-    int& go = lds.go;
+// A group of up to G stacked n x n nodes (row-major, so the group is a (G n) x n
+// row-major matrix) is factored by the wide streaming kernel in FP64 into one
+// node of the next level (Sec. 3.5: the reduce stage factors the stacked R
+// factors).  The workgroup that finishes the last group of the next level's
+// group (by ticket) climbs; the one that produces the single top node writes R
+// (rows flipped to a nonnegative diagonal) and the column sums.  `go` is a
+// workgroup-shared flag.
+template <int NW, int W, int RPLD, int G>
+__device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t group0, unsigned char* smem, int* go) {
     const int tid = (int)threadIdx.x;
-    const int k = tid / QL;                 // column of this lane's group
-    const int g = tid % QL;                 // row class of this lane
-    const bool colok = k < n;
     const int64_t nn = (int64_t)n * n;
-    const int kc = min(k, n - 1);
-
-    int64_t count = t.leaves;
-    int64_t base = 0, tbase = 0;
-    int64_t node = 2 * pair0;
-    double a[RL], b[RL];
-    bool first = true;
-    if (count == 1) node = 0;
-    while (count > 1) {
-        const int64_t parent = base + count + (node >> 1);
-        const int64_t pair = node >> 1;
-        // This workgroup may have written the node in the previous iteration
-        // with another thread-to-element mapping than the one used below.
-        __syncthreads();
-        if ((node | 1) >= count) {
-            // no partner: copy up
-            const double* src = t.nodes + (base + node) * nn;
-            double* dst = t.nodes + parent * nn;
-            for (int i = tid; i < n * n; i += W * 64) dst[i] = src[i];
-            for (int i = tid; i < n; i += W * 64) t.node_cs[parent * n + i] = t.node_cs[(base + node) * n + i];
-        } else {
-            if (!first) {
-                // Every wave wrote part of the node: each releases its own
-                // stores at agent scope before the barrier that precedes the
-                // ticket (a release by thread 0 alone would not cover them).
-                grid_release();
-                __syncthreads();
-                if (tid == 0) {
-                    const int old = __hip_atomic_fetch_add(t.tickets + tbase + pair, 1, __ATOMIC_ACQ_REL,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                    if (old == 1)
-                        __hip_atomic_store(t.tickets + tbase + pair, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    go = old == 1;
-                }
-                __syncthreads();
-                if (!go) return;
-                grid_acquire();
-            }
-            const int64_t left = base + (node & ~(int64_t)1);
-            const double* A = t.nodes + left * nn;
-            const double* B = A + nn;
-#pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                const int i = min(g + QL * r, n - 1);
-                const bool ok = colok && g + QL * r < n;
-                a[r] = ok ? A[(int64_t)i * n + kc] : 0.0;
-                b[r] = ok ? B[(int64_t)i * n + kc] : 0.0;
-            }
-            for (int j = 0; j < n; ++j) {
-                __syncthreads();
-                if (k == j) {
-#pragma unroll
-                    for (int r = 0; r < RL; ++r) sy[g + QL * r] = b[r];
-                    if (g == j % QL) sy[NMAX] = a[j / QL];
-                }
-                __syncthreads();
-                double sp = 0.0, dp = 0.0;
-#pragma unroll
-                for (int r = 0; r < RL; ++r) {
-                    const double y = sy[g + QL * r];
-                    sp = __builtin_fma(y, y, sp);
-                    dp = __builtin_fma(y, b[r], dp);
-                }
-                const double alpha = sy[NMAX];
-                const double sigma = group_sum<QL>(sp);
-                const double dot = group_sum<QL>(dp);
-                const bool live = sigma != 0.0;
-                const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
-                const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-                const double s = live ? 1.0 / (alpha - beta) : 0.0;
-                const double cb = live ? 1.0 / beta : 0.0;
-                const double tau = (beta - alpha) * cb;
-                // A(j, k) sits in lane g == j % QL, register j / QL
-                double ajk = 0.0;
-#pragma unroll
-                for (int r = 0; r < RL; ++r) ajk = (r == j / QL) ? a[r] : ajk;
-                double w = __builtin_fma(s, dot, ajk);
-                w = lane_gather(w, (tid & 63 & ~(QL - 1)) | (j % QL));   // the owner's value
-                if (k == j) w = -beta;
-                if (g == j % QL) {
-                    const double an = (k == j) ? beta : __builtin_fma(-tau, w, ajk);
-#pragma unroll
-                    for (int r = 0; r < RL; ++r) a[r] = (r == j / QL) ? an : a[r];
-                }
-                const double cw = cb * w;
-#pragma unroll
-                for (int r = 0; r < RL; ++r) b[r] = __builtin_fma(sy[g + QL * r], cw, b[r]);
-            }
-            double* dst = t.nodes + parent * nn;
-            if (colok) {
-#pragma unroll
-                for (int r = 0; r < RL; ++r) {
-                    const int i = g + QL * r;
-                    if (i < n) dst[(int64_t)i * n + k] = i <= k ? a[r] : 0.0;
-                }
-            }
-            for (int i = tid; i < n; i += W * 64)
-                t.node_cs[parent * n + i] = t.node_cs[left * n + i] + t.node_cs[(left + 1) * n + i];
+    int64_t group = group0, count = t.leaves, base = 0, tbase = 0;
+    while (true) {
+        const int64_t first = group * G;
+        const int cnt = (int)min((int64_t)G, count - first);
+        const int64_t nbase = base + count;
+        const int64_t ncount = (count + G - 1) / G;
+        WideArgs a{};
+        a.X = t.nodes + (base + first) * nn;
+        a.m = (int64_t)cnt * n;
+        a.ld = n;
+        a.slab = a.m;
+        a.nstreams = 1;
+        a.n = n;
+        a.tree = t;
+        a.tree.nodes = t.nodes + (nbase + group) * nn;
+        a.tree.node_cs = nullptr;
+        wide_slab<double, double, NW, W, RPLD, LOAD_ROW>(a, 0, smem);
+        double* cs_out = t.node_cs + (nbase + group) * n;
+        for (int c = tid; c < n; c += W * 64) {
+            double s = 0.0;
+            for (int q = 0; q < cnt; ++q) s += t.node_cs[(base + first + q) * n + c];
+            cs_out[c] = s;
         }
-        first = false;
-        tbase += count >> 1;
-        base += count;
-        count = (count + 1) >> 1;
-        node >>= 1;
+        __syncthreads();
+        if (ncount == 1) {
+            // top: R column-major with rows flipped to a nonnegative diagonal
+            const double* top = t.nodes + (nbase + group) * nn;
+            for (int i = tid; i < n * n; i += W * 64) {
+                const int r = i % n, c = i / n;
+                const double d = top[(int64_t)r * n + r];
+                const double v = top[(int64_t)r * n + c];
+                t.R[i] = c >= r ? (d < 0.0 ? -v : v) : 0.0;
+            }
+            if (t.colsum != nullptr)
+                for (int c = tid; c < n; c += W * 64) t.colsum[c] = cs_out[c];
+            return;
+        }
+        grid_release();
+        __syncthreads();
+        const int64_t ngroup = group / G;
+        const int gsize = (int)min((int64_t)G, ncount - ngroup * G);
+        if (tid == 0) {
+            const int old = __hip_atomic_fetch_add(t.tickets + tbase + ngroup, 1, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            const int last = old == gsize - 1;
+            if (last) __hip_atomic_store(t.tickets + tbase + ngroup, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *go = last;
+        }
+        __syncthreads();
+        if (!*go) return;
+        grid_acquire();
+        tbase += (ncount + G - 1) / G;
+        base = nbase;
+        count = ncount;
+        group = ngroup;
     }
-    // root: final R (column-major), rows flipped to a nonnegative diagonal
-    __syncthreads();
-    const double* rootp = t.nodes + base * nn;
-    for (int i = tid; i < n * n; i += W * 64) {
-        const int r = i % n, c = i / n;          // R(r, c) at column-major i
-        const double d = rootp[(int64_t)r * n + r];
-        const double v = rootp[(int64_t)r * n + c];
-        t.R[i] = c >= r ? (d < 0.0 ? -v : v) : 0.0;
-    }
-    if (t.colsum != nullptr)
-        for (int i = tid; i < n; i += W * 64) t.colsum[i] = t.node_cs[base * n + i];
 }
 
-template <int NMAX, int W>
-__global__ void __launch_bounds__(W * 64) tsqr_wide_tree_kernel(TreeArgs t, int n) {
-    __shared__ WideTreeLds<NMAX> lds;
-    wide_tree_run<NMAX, W>(t, n, blockIdx.x, lds);
+
+template <int NW, int W, int RPLD, int G>
+__global__ void __launch_bounds__(W * 64) tsqr_wide_merge_kernel(TreeArgs t, int n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int go;
+    wide_merge_run<NW, W, RPLD, G>(t, n, blockIdx.x, smem, &go);
 }
 
 }  // namespace tsnmf
+
+

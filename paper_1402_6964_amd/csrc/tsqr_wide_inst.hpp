@@ -1,5 +1,5 @@
 // Launch helper for the wide TSQR path (33..128 columns): the leaf kernel
-// over row slabs followed by the FP64 tree over the slab factors.
+// over row slabs followed by the G-ary FP64 tree over the slab factors.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -29,11 +29,18 @@ hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     profile_split(stream);
-    constexpr int NMAX = NW * W;
-    constexpr int TW = NMAX <= 64 ? NMAX / 16 : NMAX / 8;    // 4 or 8 lanes per column
-    const int64_t pairs = (a.tree.leaves + 1) / 2;
-    auto tk = tsqr_wide_tree_kernel<NMAX, TW>;
-    hipLaunchKernelGGL(tk, dim3((unsigned)pairs), dim3(TW * 64), 0, stream, a.tree, a.n);
+    // FP64 tree: groups of 4 stacked factors, each factored by the wide kernel
+    constexpr int G = 4;
+    constexpr int RPLD = 4;
+    using M = Wide<double, double, NW, W, RPLD>;
+    const size_t mlds = M::lds_bytes();
+    auto mk = tsqr_wide_merge_kernel<NW, W, RPLD, G>;
+    if (mlds > 65536) {
+        e = hipFuncSetAttribute((const void*)mk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t groups = (a.tree.leaves + G - 1) / G;
+    hipLaunchKernelGGL(mk, dim3((unsigned)groups), dim3(W * 64), mlds, stream, a.tree, a.n);
     return hipGetLastError();
 }
 

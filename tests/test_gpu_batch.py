@@ -184,3 +184,38 @@ def test_argument_errors(lib):
     assert lib.tsnmf_tsqr_r_batched(2, a, a, a, a, lib.F32, None) == -7
     assert lib.tsnmf_reserve_batched(0, 10) == -1
     assert lib.tsnmf_reserve_batched(4, -1) == -2
+
+
+def test_batched_workload_full_size(lib):
+    """The full batched workload (512 matrices, m log-uniform in [1e4, 2e6],
+    n in {16, 32, 64, 128}, 44.5 GB) in one graph-captured call, as bench.py
+    times it.  Every matrix: column 2-norms of R and l1 column sums against
+    FP64 sums of X on the device; R upper triangular with diag >= 0.  The
+    shortest matrix of each width: R against the oracle."""
+    shapes = synth.batch_shapes()
+    mats = [synth.batch_matrix(q, m, n, device="cuda")["X"] for q, (m, n) in enumerate(shapes)]
+    b = lib.Batch(mats)
+    b.run()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    g.replay()
+    torch.cuda.synchronize()
+    res = b.results()
+    worst_norm, worst_cs = 0.0, 0.0
+    for X, (R, cs) in zip(mats, res):
+        Rn = R.cpu().numpy()
+        assert np.all(np.tril(Rn, -1) == 0.0) and np.all(np.diag(Rn) >= 0.0)
+        X64 = X.double()
+        cn = torch.sqrt((X64 * X64).sum(0)).cpu().numpy()
+        d = X64.abs().sum(0).cpu().numpy()
+        worst_norm = max(worst_norm, float(np.max(np.abs(np.linalg.norm(Rn, axis=0) - cn) / cn)))
+        worst_cs = max(worst_cs, float(np.max(np.abs(cs.cpu().numpy() - d) / d)))
+        del X64
+    assert worst_norm <= 1e-5, worst_norm
+    assert worst_cs <= 1e-6, worst_cs
+    for n in (16, 32, 64, 128):
+        q = min((i for i, s in enumerate(shapes) if s[1] == n), key=lambda i: shapes[i][0])
+        Xh = mats[q].cpu().numpy()
+        _check(res[q][0].cpu().numpy(), res[q][1].cpu().numpy(), Xh, name=f"{shapes[q]}")

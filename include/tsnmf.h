@@ -85,11 +85,14 @@ extern "C" {
  *   colsum  device FP64[n] or NULL; output colsum[j] = sum_i |X(i, j)|.
  *
  * Row blocks are factored by Householder reflections in the input precision
- * (FP32 for F32 input unless TSNMF_LEAF_F64), each wave keeping a running R
- * for its contiguous slab of rows (the leaf); the leaf factors are combined by
- * a binary tree of FP64 QR factorisations of stacked triangles, all in one
- * kernel launch.  The result is deterministic for a given (m, n, flags,
- * configuration).
+ * (FP32 for F32 input unless TSNMF_LEAF_F64), one wave (n <= 32) or one
+ * workgroup (n > 32) keeping a running FP64 R for its contiguous slab of rows
+ * (the leaf).  The leaf factors are then combined by a tree of FP64 QR
+ * factorisations of stacked factors (groups of several factors per node), in
+ * a second launch that climbs all levels by ticket.  The result is
+ * deterministic for a given (m, n, flags, configuration).
+ * Errors: -1 X NULL, -2 m < 1, -3 n < 1, -4 ld too small, -5 flags, -6 R NULL,
+ * TSNMF_ERR_UNSUPPORTED for n > TSNMF_MAX_N.
  */
 int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
                  double* R, double* colsum, hipStream_t stream);
@@ -101,7 +104,8 @@ typedef struct tsnmf_tsqr_config {
     int32_t tree_arity;     /* slab factors merged per tree node, 2..64 (2 = a
                                binary tree); n <= 32 only, capped at the most
                                stacked rows one workgroup pass holds; the wider
-                               paths use a binary tree.  0 = library default. */
+                               path merges 4 per node.  0 = library default.
+                               Other values: -8 from tsnmf_tsqr_r_ex.        */
     int32_t rows_per_lane;  /* reserved, must be 0: the row block height is fixed
                                per width when the library is compiled        */
 } tsnmf_tsqr_config;
@@ -189,13 +193,15 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
  * M diag(1/colscale): r times pick j* = argmax_j ||Z(:, j)||_2^2 over columns
  * not yet picked (ties -> smallest j), then Z <- Z - u (u^T Z) with
  * u = Z(:, j*) / ||Z(:, j*)||.  Z starts as M diag(1/colscale).
- *   M         device FP64, p x n column-major (ldm >= p), p, n in 1..TSNMF_MAX_N*2
+ *   M         device FP64, p x n column-major (ldm >= p), p and n in 1..256
  *   colscale  device FP64[n] or NULL (no scaling); e.g. the colsum of tsnmf_tsqr_r
  *   r         1..n picks
  *   K         device int32[r] output, in selection order
  *   score     device FP64[r] or NULL: the winning ||Z(:, j*)||^2 of each pick
  *   info      device int32[1] output: number of columns picked (< r if the best
  *             score reached exactly 0 first; remaining K entries are -1)
+ * Errors: -1 M NULL, -2 p, -3 n out of range, -4 ldm < p, -6 r outside 1..n,
+ * -7 K NULL, -9 info NULL.
  */
 int tsnmf_select_spa(const double* M, int32_t p, int32_t n, int32_t ldm,
                      const double* colscale, int32_t r, int32_t* K, double* score,

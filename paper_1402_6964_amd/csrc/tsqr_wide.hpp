@@ -4,16 +4,15 @@
 //
 // The algebra is that of the small kernel (structured Householder on
 // [R; B], tsqr_small.hpp), spread over waves by columns: at step j the wave
-// that owns column j publishes the pivot column B(:, j) and alpha = R(j, j)
-// through LDS (double-buffered, one block barrier per step); every wave forms
-// sigma = ||B(:, j)||^2 with one all-reduce, the dot products with its own
-// columns with one reduce-scatter butterfly, applies the reflector to its own
-// columns and keeps its own part of R(j, :) in LDS.  All waves use the same
-// sigma and alpha, so the reflector is identical in every wave.  Steps come
-// in rounds of W with the same local pivot column (Wide::level): the round
-// index is a compile-time constant, so the pivot is read straight from its
-// registers and the finished columns left of it drop out of the dot products
-// and updates.
+// that owns column j forms sigma = ||B(:, j)||^2 (one all-reduce) and the
+// reflector scalars from alpha = R(j, j) in FP64, and publishes them with the
+// pivot column B(:, j) through LDS (double-buffered, one block barrier per
+// step); every wave then forms the dot products with its own columns with one
+// reduce-scatter butterfly, applies the reflector to its own columns and keeps
+// its own part of R(j, :) in LDS.  Steps come in rounds of W with the same
+// local pivot column (Wide::level): the round index is a compile-time
+// constant, so the pivot is read straight from its registers and the finished
+// columns left of it drop out of the dot products and updates.
 #pragma once
 #include "tsqr_small.hpp"
 
@@ -40,7 +39,8 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
     static constexpr int NMAX = NW * W;
     static constexpr int RW = NMAX * NW - W * NW * (NW - 1) / 2 + NMAX;   // FP64 slots per wave (bound)
     static constexpr size_t pv_elems() { return (size_t)2 * (RPL * 64 + 1); } // two pivot slots (T)
-    static constexpr size_t lds_bytes() { return ((size_t)W * RW + 2) * 8 + pv_elems() * sizeof(T); }
+    static constexpr int NS = 8;                      // published reflector scalars per slot (FP64)
+    static constexpr size_t lds_bytes() { return ((size_t)W * RW + 2 * NS) * 8 + pv_elems() * sizeof(T); }
 
     // The W steps j = Q W + o (o = 0 .. W-1) whose pivot is local column Q of
     // wave o.  Q is a compile-time index, so the pivot is read straight from
@@ -62,22 +62,37 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                 if (j >= n) break;
                 const int c0 = Q + (wv < o ? 1 : 0); // first live local column of this wave
                 T* slot = pv + (j & 1) * (RPL * 64 + 1);
+                double* sc = apub + (j & 1) * NS;    // this step's reflector scalars
                 if (wv == o) {
+                    // The owner holds the whole pivot column: it alone forms
+                    // sigma and the reflector scalars (FP64) and publishes
+                    // them with the column, so the other waves skip both.
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) slot[r * 64 + L] = x[r][Q];
-                    // R(j, j) is the first entry of the owner's row j; it is
-                    // overwritten in this step, so it is published before the barrier
-                    if (L == 0) apub[j & 1] = Rw[off];
+                    T sg = x[0][Q] * x[0][Q];
+#pragma unroll
+                    for (int r = 1; r < RPL; ++r) sg = fma_t(x[r][Q], x[r][Q], sg);
+                    const double sigma = (double)wave_sum(sg);
+                    const double alpha = Rw[off];    // R(j, j): first entry of the owner's row j
+                    const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
+                    const bool lv = sigma != 0.0;
+                    const double beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+                    const double inv_beta = rcp_fast<double>(beta);
+                    if (L == 0) {
+                        sc[0] = beta;
+                        sc[1] = lv ? rcp_fast<double>(alpha - beta) : 0.0;   // s = 1 / (alpha - beta)
+                        sc[2] = lv ? (beta - alpha) * inv_beta : 0.0;        // tau
+                        sc[3] = lv ? inv_beta : 0.0;                         // 1 / beta for the block update
+                    }
                 }
                 __syncthreads();
                 T xp[RPL];
 #pragma unroll
                 for (int r = 0; r < RPL; ++r) xp[r] = slot[r * 64 + L];
-                const double alpha = apub[j & 1];
-                T sg = xp[0] * xp[0];
-#pragma unroll
-                for (int r = 1; r < RPL; ++r) sg = fma_t(xp[r], xp[r], sg);
-                const double sigma = (double)wave_sum(sg);
+                const double beta = sc[0];
+                const double s = sc[1];
+                const double tau = sc[2];
+                const T cb = (T)sc[3];
                 T p[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
@@ -95,13 +110,6 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                 const bool mine = vi < CNT && c >= c0;
                 const bool piv = wv == o && vi == 0;
                 const double rj = mine ? Rw[off + c - c0] : 0.0;
-                const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
-                const bool live = sigma != 0.0;
-                const double beta = live ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-                const double inv_beta = rcp_fast<double>(beta);
-                const double s = live ? rcp_fast<double>(alpha - beta) : 0.0;
-                const double tau = live ? (beta - alpha) * inv_beta : 0.0;
-                const T cb = live ? (T)inv_beta : T(0);
                 double w = __builtin_fma(s, (double)D, rj);
                 if (piv) w = -beta;
                 double rn = __builtin_fma(-tau, w, rj);
@@ -133,8 +141,8 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     const int L = lane_id();
     const int n = a.n;
     double* Rw = (double*)smem + (size_t)wv * S::RW;  // this wave's part of R (compact rows)
-    double* apub = (double*)smem + (size_t)W * S::RW;  // alpha of steps j (two slots by parity)
-    T* pv = (T*)(apub + 2);
+    double* apub = (double*)smem + (size_t)W * S::RW;  // reflector scalars of steps j (two slots by parity)
+    T* pv = (T*)(apub + 2 * S::NS);
 
     for (int i = L; i < S::RW; i += 64) Rw[i] = 0.0;
 

@@ -120,10 +120,14 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
     for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows) {
         __syncthreads();
         if (col_ld < n) {
+            // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply
+            // per chunk, then one add per row
+            const int64_t ib = i0 + rgrp * 8;
+            int64_t idx = ib * a.ld + col_ld;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int64_t i = i0 + rgrp * 8 + t;
-                const float v = i < r1 ? load_f32(a.X, i * a.ld + col_ld, bf16_in) : 0.0f;
+                const float v = ib + t < r1 ? load_f32(a.X, idx, bf16_in) : 0.0f;
+                idx += a.ld;
                 csum += (double)__builtin_fabsf(v);
                 xs[col_ld * kMfmaRows + rgrp * 8 + t] = (__bf16)v;   // round to nearest even
             }

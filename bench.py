@@ -220,9 +220,9 @@ def extras(torch, tsnmf, synth, dev, check=True):
 
     heat()
     tsnmf.tsnmf_profile_query(0)
-    tsnmf.tsnmf_profile_enable(True)
+    tsnmf.tsnmf_profile_enable(2)
     t = _timed(torch, heat, 5)
-    tsnmf.tsnmf_profile_enable(False)
+    tsnmf.tsnmf_profile_enable(0)
     _, lms, lcalls = tsnmf.tsnmf_profile_query(0)
     tsnmf.tsnmf_profile_query(1)
     hb = m * n * 4
@@ -318,15 +318,24 @@ def main():
     torch.cuda.synchronize()
     tsnmf.tsnmf_profile_query(0)
     tsnmf.tsnmf_profile_query(1)
-    tsnmf.tsnmf_profile_enable(True)
+    # timed region: the library records two HIP events per call on the launch
+    # stream, around the leaf kernel only (the least intrusive mode)
+    tsnmf.tsnmf_profile_enable(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tsnmf.tsnmf_profile_enable(False)
+    tsnmf.tsnmf_profile_enable(0)
     _, leaf_ms, leaf_calls = tsnmf.tsnmf_profile_query(0)
+    # the reduction tree's time, from a short separate pass with every stage timed
+    tsnmf.tsnmf_profile_enable(1)
+    for _ in range(min(args.steps, 20)):
+        step()
+    torch.cuda.synchronize()
+    tsnmf.tsnmf_profile_enable(0)
+    tsnmf.tsnmf_profile_query(0)
     _, tail_ms, tail_calls = tsnmf.tsnmf_profile_query(1)
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps

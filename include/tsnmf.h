@@ -261,11 +261,13 @@ int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int
    before graph capture).  Host call, synchronous. */
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
 
-/* Profiling aid.  While enabled (on != 0), TSQR and projection calls record
-   HIP events on their stream around their main kernel ("stage 0": the leaf /
+/* Profiling aid.  While enabled, TSQR and projection calls record HIP
+   events on their stream around their main kernel ("stage 0": the leaf /
    projection kernel; for the batched call the persistent kernel, trees
-   included) and around the rest of the call ("stage 1": reduction tree and
-   finalisation; for the batched call the device planner).
+   included) and, with on = 1, also around the rest of the call ("stage 1":
+   reduction tree and finalisation; for the batched call the device planner).
+   on = 2 records stage 0 only (two events per call, the least intrusive);
+   on = 0 stops recording.
    tsnmf_profile_query waits for the recorded events (host synchronisation),
    returns the summed elapsed milliseconds and the number of calls of a
    stage, and clears that stage.  Not for graph capture. */

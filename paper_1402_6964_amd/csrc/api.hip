@@ -53,11 +53,12 @@ struct ProfileStage {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+int g_prof_mode = 0;           // 0 off, 1 every stage, 2 the main kernel only
 ProfileStage g_prof[2];
 }  // namespace
 
-bool profiling_on() { return g_prof_on; }
+bool profiling_on() { return g_prof_mode != 0; }
+bool profiling_all() { return g_prof_mode == 1; }
 
 int profile_event(hipStream_t s, hipEvent_t* ev) {
     TSNMF_HIP(hipEventCreate(ev));
@@ -70,8 +71,10 @@ thread_local hipEvent_t g_split[2] = {nullptr, nullptr};
 }
 
 void profile_split(hipStream_t s) {
-    if (!g_prof_on) return;
-    for (auto& e : g_split) {
+    if (g_prof_mode == 0) return;
+    for (int q = 0; q < 2; ++q) {
+        hipEvent_t& e = g_split[q];
+        if (q == 1 && g_prof_mode != 1) break;   // the second stage is not timed
         if (e != nullptr) (void)hipEventDestroy(e);
         e = nullptr;
         if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, s) != hipSuccess) {
@@ -83,7 +86,7 @@ void profile_split(hipStream_t s) {
 }
 
 bool profile_take_split(hipEvent_t* end0, hipEvent_t* begin1) {
-    const bool ok = g_split[0] != nullptr && g_split[1] != nullptr;
+    const bool ok = g_split[0] != nullptr && (g_split[1] != nullptr || g_prof_mode == 2);
     if (ok) {
         *end0 = g_split[0];
         *begin1 = g_split[1];
@@ -277,7 +280,7 @@ int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
 }
 
 int tsnmf_profile_enable(int on) {
-    g_prof_on = on != 0;
+    g_prof_mode = on == 2 ? 2 : (on != 0 ? 1 : 0);
     return TSNMF_OK;
 }
 

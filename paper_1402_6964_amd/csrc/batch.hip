@@ -482,20 +482,24 @@ int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const i
     const int64_t tcap = ws.tcap, dcap = ws.dcap;
 
     const bool prof = profiling_on();
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-    if (prof)
-        if (int st = profile_event(stream, &e0)) return st;
+    const bool prof_all = prof && profiling_all();
+    hipEvent_t p0 = nullptr, p1 = nullptr, e0 = nullptr, e1 = nullptr;
+    if (prof_all)
+        if (int st = profile_event(stream, &p0)) return st;
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, (int)B, X, m, n, ld, R, colsum,
                        hdr, mats, iprefix, tk, tcap, wd, dcap);
     TSNMF_LAUNCH_CHECK();
+    if (prof_all) {
+        if (int st = profile_event(stream, &p1)) return st;
+        profile_record(1, p0, p1);           // planner
+    }
     if (prof)
-        if (int st = profile_event(stream, &e1)) return st;
+        if (int st = profile_event(stream, &e0)) return st;
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kWaves * 64), kLds, stream, hdr, mats, iprefix, (int)B);
     TSNMF_LAUNCH_CHECK();
     if (prof) {
-        if (int st = profile_event(stream, &e2)) return st;
-        profile_record(1, e0, e1);
-        profile_record(0, e1, e2);
+        if (int st = profile_event(stream, &e1)) return st;
+        profile_record(0, e0, e1);           // persistent kernel
     }
     return TSNMF_OK;
 }

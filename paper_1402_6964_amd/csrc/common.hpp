@@ -38,6 +38,7 @@ size_t gp_workspace_bytes(int64_t m, int n, int k);
 // Profiling (see tsnmf_profile_enable): profile_event creates and records an
 // event on the stream; profile_record files a (start, stop) pair under a stage.
 bool profiling_on();
+bool profiling_all();    // also the stages after the main kernel
 int profile_record(int stage, hipEvent_t start, hipEvent_t stop);
 int profile_event(hipStream_t s, hipEvent_t* ev);
 // Called by launch helpers between a leaf kernel and its tree kernel: while

@@ -318,17 +318,19 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
         hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
     }
     TSNMF_LAUNCH_CHECK();
+    const bool prof_all = prof && profiling_all();
     if (prof) {
         if (int st = profile_event(stream, &e1)) return st;
-        if (int st = profile_event(stream, &e2)) return st;
+        profile_record(0, e0, e1);
+        if (prof_all)
+            if (int st = profile_event(stream, &e2)) return st;
     }
     const int64_t outs = (int64_t)k * n;
     hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream, a.part, parts, k,
                        n, Y, a.part_cs, colsum);
     TSNMF_LAUNCH_CHECK();
-    if (prof) {
+    if (prof_all) {
         if (int st = profile_event(stream, &e3)) return st;
-        profile_record(0, e0, e1);
         profile_record(1, e2, e3);
     }
     return TSNMF_OK;

@@ -164,12 +164,15 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
         TSNMF_HIP(launch_leaf(p.path, p.load, n, a, stream));
     }
     if (prof) {
-        if (int st = profile_event(stream, &e1)) return st;
         hipEvent_t m0 = nullptr, m1 = nullptr;
         if (profile_take_split(&m0, &m1)) {
             profile_record(0, e0, m0);       // leaf kernel
-            profile_record(1, m1, e1);       // reduction tree
+            if (m1 != nullptr) {
+                if (int st = profile_event(stream, &e1)) return st;
+                profile_record(1, m1, e1);   // reduction tree
+            }
         } else {
+            if (int st = profile_event(stream, &e1)) return st;
             profile_record(0, e0, e1);
         }
     }

@@ -151,7 +151,8 @@ def tsnmf_reserve(max_m, max_n, max_k=0):
 
 
 def tsnmf_profile_enable(on):
-    return _profile_enable(1 if on else 0)
+    """on: 0/False off, 1/True every stage, 2 the main kernel only."""
+    return _profile_enable(on if on in (0, 1, 2) and not isinstance(on, bool) else (1 if on else 0))
 
 
 def tsnmf_profile_query(stage):

@@ -268,3 +268,18 @@ def test_tree_group_sizes_match_oracle(lib, n):
         cfg = lib.TsqrConfig(leaf_rows=1024, tree_arity=arity, rows_per_lane=0)
         Rg, csg = _run(lib, Xd, config=cfg)
         _check_against_oracle(Rg, csg, Xh, 1e-6, 2e-5, 1e-6, norm_tol=1e-5)
+
+
+def test_profiling_modes(lib):
+    """on = 1 times the leaf and the tree; on = 2 the leaf only."""
+    X = synth.random_matrix(200_000, 25, dtype=torch.float32, seed_tag=70).cuda()
+    for mode, tree_calls in ((1, 3), (2, 0)):
+        lib.tsnmf_profile_query(0)
+        lib.tsnmf_profile_query(1)
+        lib.tsnmf_profile_enable(mode)
+        for _ in range(3):
+            lib.tsqr_r(X)
+        lib.tsnmf_profile_enable(0)
+        st0, ms0, c0 = lib.tsnmf_profile_query(0)
+        st1, ms1, c1 = lib.tsnmf_profile_query(1)
+        assert st0 == 0 and st1 == 0 and c0 == 3 and c1 == tree_calls and ms0 > 0.0

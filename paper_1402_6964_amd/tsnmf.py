@@ -198,9 +198,18 @@ def colmajor_square(buf):
 
 
 def tsqr_r(X, leaf_f64=False, config=None, stream=None, with_colsum=True):
-    """R (n x n, FP64, diag >= 0) and the l1 column sums of a CUDA tensor X."""
+    """R (n x n, FP64, diag >= 0) and the l1 column sums of a CUDA tensor X.
+
+    config: None (library default), a TsqrConfig, or "tuned" for the entry the
+    autotuner (tune.py) recorded for X's shape, if any."""
     m, n = X.shape
     lay, ld = _layout(X)
+    if isinstance(config, str):
+        if config != "tuned":
+            raise ValueError("config must be None, a TsqrConfig or 'tuned'")
+        from . import tune
+        dt = {torch.float32: "f32", torch.float64: "f64"}.get(X.dtype, "other")
+        config = tune.lookup(dt, "col" if lay == COL_MAJOR else "row", n, m)
     flags = _DTYPE_FLAG[X.dtype] | lay | (LEAF_F64 if leaf_f64 else 0)
     Rbuf = torch.empty((n, n), dtype=torch.float64, device=X.device)
     cs = torch.empty(n, dtype=torch.float64, device=X.device) if with_colsum else None

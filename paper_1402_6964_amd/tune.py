@@ -1,14 +1,15 @@
-"""Autotuner for the TSQR launch geometry (leaf height and row block size).
+"""Autotuner for the TSQR launch geometry (leaf height and tree arity).
 
     python -m paper_1402_6964_amd.tune --m 10000000 --n 25 [--dtype f32] [--layout row]
 
 For one input shape it times tsnmf_tsqr_r_ex over a grid of leaf heights
-(rows per slab) with HIP events, rejects any configuration whose R differs
+(rows per slab) and, for n <= 32, tree group sizes (slab factors merged per
+tree node) with HIP events.  It rejects any configuration whose R differs
 from the default configuration's by more than the rounding bound of the
 precision used (every configuration computes the same R up to rounding), and
 records the fastest in paper_1402_6964_amd/tuned.json, keyed by
-(dtype, layout, n, floor(log2 m)).  The Python binding's tsqr_r() looks the
-key up when no explicit configuration is given.
+(dtype, layout, n, floor(log2 m)).  tsnmf.tsqr_r(X, config="tuned") applies
+the recorded entry for X's key (the library default when there is none).
 """
 
 import argparse
@@ -39,7 +40,7 @@ def lookup(dtype, layout, n, m):
     e = load().get(key(dtype, layout, n, m))
     if e is None:
         return None
-    return tsnmf.TsqrConfig(leaf_rows=int(e["leaf_rows"]), tree_arity=0, rows_per_lane=0)
+    return tsnmf.TsqrConfig(leaf_rows=int(e["leaf_rows"]), tree_arity=int(e.get("tree_arity", 0)), rows_per_lane=0)
 
 
 def time_config(X, cfg, reps=20):
@@ -59,29 +60,35 @@ def time_config(X, cfg, reps=20):
     return ev0.elapsed_time(ev1) / reps, Rbuf.t().cpu()
 
 
-def tune(X, leaf_grid=None, verbose=True):
+def tune(X, leaf_grid=None, arity_grid=None, verbose=True):
     m, n = X.shape
     lay, _ = tsnmf._layout(X)
     t0, R0 = time_config(X, None)
     tol = 1e-5 if X.dtype == torch.float32 else 1e-11
     if leaf_grid is None:
-        leaf_grid = sorted({max(64, m // p) for p in (64, 128, 256, 512, 768, 1024, 1536, 2048, 3072, 4096)})
-    best = (t0, 0)
-    results = [{"leaf_rows": 0, "ms": t0}]
+        leaf_grid = [0] + sorted({max(64, m // p) for p in (256, 512, 1024, 1536, 2048, 3072, 4096)})
+    if arity_grid is None:
+        arity_grid = [0, 8, 12, 16, 20, 24, 32] if n <= 32 else [0]
+    best = (t0, 0, 0)
+    results = [{"leaf_rows": 0, "tree_arity": 0, "ms": t0}]
     for leaf in leaf_grid:
-        cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=0, rows_per_lane=0)
-        ms, R = time_config(X, cfg)
-        err = float((R - R0).abs().max() / R0.abs().max())
-        ok = err <= tol
-        results.append({"leaf_rows": int(leaf), "ms": ms, "err": err, "ok": ok})
-        if verbose:
-            print(f"leaf_rows {leaf:9d}  {ms:8.3f} ms  {m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}",
-                  flush=True)
-        if ok and ms < best[0]:
-            best = (ms, int(leaf))
+        for ar in arity_grid:
+            if leaf == 0 and ar == 0:
+                continue
+            cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=int(ar), rows_per_lane=0)
+            ms, R = time_config(X, cfg)
+            err = float((R - R0).abs().max() / R0.abs().max())
+            ok = err <= tol
+            results.append({"leaf_rows": int(leaf), "tree_arity": int(ar), "ms": ms, "err": err, "ok": ok})
+            if verbose:
+                print(f"leaf_rows {leaf:9d} arity {ar:3d}  {ms:8.3f} ms  "
+                      f"{m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}", flush=True)
+            if ok and ms < best[0]:
+                best = (ms, int(leaf), int(ar))
     dt = {torch.float32: "f32", torch.float64: "f64"}[X.dtype]
     lname = "col" if lay == tsnmf.COL_MAJOR else "row"
-    return key(dt, lname, n, m), {"leaf_rows": best[1], "ms": best[0], "default_ms": t0}, results
+    entry = {"leaf_rows": best[1], "tree_arity": best[2], "ms": best[0], "default_ms": t0}
+    return key(dt, lname, n, m), entry, results
 
 
 def main():

@@ -155,11 +155,6 @@ template <int P> __device__ __forceinline__ int bfly_vidx(int L) {
     for (int s = 0; s < P; ++s) v |= ((L >> (5 - s)) & 1) << s;
     return v;
 }
-__device__ __forceinline__ int bfly_vidx_rt(int L, int P) {
-    int v = 0;
-    for (int s = 0; s < P; ++s) v |= ((L >> (5 - s)) & 1) << s;
-    return v;
-}
 // Lowest lane holding value v after butterfly<P> (compile-time usable).
 constexpr int bfly_lane(int v, int P) {
     int L = 0;

@@ -73,11 +73,14 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     if (dt == TSNMF_F64) p.path = Path::F64;
     else p.path = (flags & TSNMF_LEAF_F64) ? Path::F32W : Path::F32;
     p.wide = n > 32;
-    p.waves = !p.wide ? 1 : (n <= 64 ? 4 : 8);
     if (col) p.load = LOAD_COL;
     else if (ld == n && p.path != Path::F32W && !p.wide) p.load = LOAD_ROW_STAGED;
     else p.load = LOAD_ROW;
-    const int rpl = p.wide ? (p.path == Path::F32 ? 8 : 4)
+    // wide: 8 waves above 64 columns; up to 64, 8 for FP32 column-major input
+    // (8 columns x 16 rows per lane), else 4 (16 columns per wave)
+    const bool f32_8x8 = p.path == Path::F32 && n <= 64 && col;
+    p.waves = !p.wide ? 1 : (n > 64 || f32_8x8 ? 8 : 4);
+    const int rpl = p.wide ? (p.path == Path::F32 ? (f32_8x8 ? 16 : 8) : 4)
                            : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
                                                   : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
     p.block_rows = 64LL * rpl;

@@ -14,10 +14,8 @@ namespace tsnmf {
 // cost (reflector scalars, pivot exchange, barrier) over.
 template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 8 : 4; }
 
-template <typename T, typename TI, int W, int LOAD>
+template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_rpl<T>()>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
-    constexpr int NW = 16;
-    constexpr int RPL = wide_rpl<T>();
     using S = Wide<T, TI, NW, W, RPL>;
     const size_t lds = S::lds_bytes();
     auto kern = tsqr_wide_kernel<T, TI, NW, W, RPL, LOAD>;

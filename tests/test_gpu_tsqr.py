@@ -225,6 +225,34 @@ def test_wide_fp32_input_fp64_leaves(lib):
     _check_against_oracle(Rg, csg, X.numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
 
 
+@pytest.mark.parametrize("n,dt", [(48, torch.float32), (100, torch.float32), (64, torch.float64), (90, torch.float64)])
+def test_wide_rowmajor_strided(lib, n, dt):
+    """A column window of a wider row-major array (ld = n + 7, offset 3)."""
+    m = 30_011
+    store = synth.random_matrix(m, n + 7, dtype=dt, seed_tag=25, dist="uniform")
+    X = store[:, 3:3 + n]
+    Rg, csg = _run(lib, store.cuda()[:, 3:3 + n])
+    f32 = dt == torch.float32
+    _check_against_oracle(Rg, csg, X.numpy(), 1e-6 if f32 else 1e-12, 5e-5 if f32 else 1e-10,
+                          1e-6 if f32 else 1e-13, norm_tol=1e-5 if f32 else 1e-12)
+
+
+@pytest.mark.parametrize("m,n", [(1, 33), (40, 64), (65, 70), (129, 128), (1000, 40)])
+def test_wide_short_inputs(lib, m, n):
+    """Fewer rows than one 64-row chunk, one chunk plus a ragged tail, and
+    inputs shorter than the block: the rows past m enter as zeros."""
+    for dt in (torch.float32, torch.float64):
+        X = synth.random_matrix(m, n, dtype=dt, seed_tag=26, dist="uniform")
+        Rg, csg = _run(lib, X.cuda())
+        X64 = X.numpy().astype(np.float64)
+        f32 = dt == torch.float32
+        assert np.all(np.tril(Rg, -1) == 0.0)
+        g = _rel_gram(Rg, X64)
+        assert g <= (1e-6 if f32 else 1e-12), f"m={m} n={n} {dt}: gram error {g:.3e}"
+        d = np.abs(X64).sum(axis=0)
+        assert np.max(np.abs(csg - d) / d) <= (1e-6 if f32 else 1e-13)
+
+
 def test_wide_tree_shapes(lib):
     """Leaf counts 1, 2, 3, 5 and 37 exercise odd nodes at several levels."""
     X = synth.random_matrix(30_000, 70, dtype=torch.float32, seed_tag=24).cuda()

@@ -57,6 +57,20 @@ template <typename T> __device__ __forceinline__ T sqrt_t(T x);
 template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return __builtin_sqrtf(x); }
 template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return __builtin_sqrt(x); }
 
+// sqrt(x) for x in the normal FP64 range (not zero, not infinite): the
+// hardware reciprocal-square-root estimate refined by one coupled Newton step
+// for g = sqrt(x) and h = 1 / (2 sqrt(x)) (Goldschmidt's iteration), then one
+// residual correction of g, so the result is within an ulp or two.
+__device__ __forceinline__ double sqrt_normal(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
+
 // T: arithmetic of the block (its dot products and updates); TI: input
 // element type; R, alpha, sigma and the reflector scalars are kept in FP64
 // (TR), so that the running factor of a long slab does not accumulate FP32
@@ -74,12 +88,17 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     static constexpr int RS = roff(N);                    // R slots per wave (elements of T)
     static constexpr int SS = (N % 2) ? N : N + 1;        // staging row stride, odd -> no bank conflicts
     static constexpr int STG = 64 * SS;                   // staging elements (TI) per wave
+    // w slot per wave (T): one value per butterfly index, 16-byte multiple
+    static constexpr int BCE = (int)(((pow2ceil(N) * sizeof(T) + 15) & ~(size_t)15) / sizeof(T));
     // LDS of a workgroup of `wpg` waves: every wave's R, then every wave's
-    // staging area
+    // staging area (staged loads only), then every wave's w slot
     static constexpr size_t r_bytes(int wpg = 4) { return (size_t)wpg * RS * sizeof(TR); }
     static constexpr size_t stage_off(int wpg = 4) { return (r_bytes(wpg) + 15) & ~(size_t)15; }
+    static constexpr size_t bc_off(bool staged, int wpg = 4) {
+        return stage_off(wpg) + (staged ? ((size_t)wpg * STG * sizeof(TI) + 15) & ~(size_t)15 : 0);
+    }
     static constexpr size_t lds_bytes(bool staged, int wpg = 4) {
-        return stage_off(wpg) + (staged ? (size_t)wpg * STG * sizeof(TI) : 0);
+        return bc_off(staged, wpg) + (size_t)wpg * BCE * sizeof(T);
     }
 
     // ---- one Householder step (column J) -------------------------------------
@@ -87,8 +106,15 @@ template <typename T, typename TI, int N, int RPL> struct Small {
     // same block: after its butterfly each wave publishes its 64 lane values,
     // and every wave adds all W of them in wave order (the same sums in every
     // wave, so the W copies of R stay identical).
-    template <int J, int W = 1>
-    static __device__ __forceinline__ void step(T (&x)[RPL][N], TR* Rl, T* xchg = nullptr) {
+    // LB: `wb` is the wave's w slot (BCE elements, 16-byte aligned); the
+    // lanes store w_{J+v} at index v (padding indices v >= n - J get w = 0,
+    // never read) and every lane reads all of them back with 16-byte
+    // broadcast reads, which keeps the per-column broadcasts off the vector
+    // ALU (the leaf, bound by vector issue).  Without LB each w_k is read
+    // from its lane into a scalar register, which is shorter in latency (the
+    // tree, bound by the latency of its steps).
+    template <int J, int W = 1, bool LB = true>
+    static __device__ __forceinline__ void step(T (&x)[RPL][N], TR* Rl, T* xchg, T* wb) {
         if constexpr (J < N) {
             constexpr int CNT = N - J;
             constexpr int V = pow2ceil(CNT);
@@ -122,11 +148,24 @@ template <typename T, typename TI, int N, int RPL> struct Small {
             const TR DR = (TR)D;
             const TR sigma = lane_bcast(DR, 0);
             const TR alpha = lane_bcast(rj, 0);
-            const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
             const bool live = sigma != TR(0);
-            const TR beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
-            const TR inv_beta = rcp_fast<TR>(beta);
-            const TR s = live ? rcp_fast<TR>(alpha - beta) : TR(0);       // 1 / (alpha - beta)
+            TR beta, inv_beta, s;
+            if constexpr (sizeof(T) == 4) {
+                // FP32 block: sigma is a nonzero FP32 value when live, so
+                // alpha^2 + sigma and beta (alpha - beta) lie far inside the
+                // normal FP64 range, and one reciprocal serves both scalars.
+                const TR nrm = sqrt_normal(fma_t(alpha, alpha, sigma));
+                beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
+                const TR amb = alpha - beta;
+                const TR q = rcp_fast<TR>(beta * amb);                      // unused unless live
+                inv_beta = amb * q;
+                s = live ? beta * q : TR(0);                                // 1 / (alpha - beta)
+            } else {
+                const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
+                beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
+                inv_beta = rcp_fast<TR>(beta);
+                s = live ? rcp_fast<TR>(alpha - beta) : TR(0);
+            }
             const TR tau = live ? (beta - alpha) * inv_beta : TR(0);
             const T c = live ? (T)inv_beta : T(0);                        // = -tau * s
             const TR w = fma_t(s, DR, rj);
@@ -134,16 +173,44 @@ template <typename T, typename TI, int N, int RPL> struct Small {
             if (vi == 0) rn = beta;
             row[vi] = rn;
             const T wt = (T)w;
+            if constexpr (LB) {
+                wb[vi] = wt;                         // lanes sharing vi store the same value
+                wave_lds_sync();
+            }
             T t[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) t[r] = c * x[r][J];
+            if constexpr (!LB) {
 #pragma unroll
-            for (int v = 1; v < CNT; ++v) {
-                const T wk = lane_bcast(wt, bfly_lane(v, P));
+                for (int v = 1; v < CNT; ++v) {
+                    const T wk = lane_bcast(wt, bfly_lane(v, P));
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
+                    for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
+                }
+            } else {
+                const T* wr = (const T*)__builtin_assume_aligned(wb, 16);
+                constexpr int E = 16 / (int)sizeof(T);   // values per 16-byte read
+#pragma unroll
+                for (int q = 0; q < (CNT + E - 1) / E; ++q) {
+                    T wq[E];
+                    if constexpr (E == 4) {
+                        const float4 f = ((const float4*)wr)[q];
+                        wq[0] = f.x; wq[1] = f.y; wq[2] = f.z; wq[3] = f.w;
+                    } else {
+                        const double2 f = ((const double2*)wr)[q];
+                        wq[0] = f.x; wq[1] = f.y;
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int v = q * E + e;
+                        if (v >= 1 && v < CNT) {
+#pragma unroll
+                            for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wq[e], x[r][J + v]);
+                        }
+                    }
+                }
             }
-            step<J + 1, W>(x, Rl, xchg);
+            step<J + 1, W, LB>(x, Rl, xchg, wb);
         }
     }
 
@@ -260,6 +327,7 @@ __device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, uns
     const int L = lane_id();
     double* Rl = (double*)smem + wv * S::RS;
     TI* St = (TI*)(smem + S::stage_off(WPG)) + wv * S::STG;
+    T* wb = (T*)(smem + S::bc_off(LOAD == LOAD_ROW_STAGED, WPG)) + wv * S::BCE;
 
     for (int i = L; i < S::RS; i += 64) Rl[i] = 0.0;
     wave_lds_sync();
@@ -283,14 +351,14 @@ __device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, uns
             T x[RPL][N];
             S::load_staged_buf(x, rs, (int)((b0 - r0) * N * (int64_t)sizeof(TI)), St);
             S::colsum_block(x, acc);
-            S::template step<0>(x, Rl);
+            S::template step<0>(x, Rl, nullptr, wb);
         }
     } else {
         for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
             T x[RPL][N];
             S::template load<LOAD>(x, a, b0, r1, St);
             S::colsum_block(x, acc);
-            S::template step<0>(x, Rl);
+            S::template step<0>(x, Rl, nullptr, wb);
         }
     }
     wave_lds_sync();
@@ -337,8 +405,10 @@ template <int N, int W_ = 8> struct CoopTree {
 };
 
 template <int N, int W = 8> struct CoopTreeLds {
-    double sR[W][Small<double, double, N, CoopTree<N, W>::RPL>::RS];
+    using S = Small<double, double, N, CoopTree<N, W>::RPL>;
+    double sR[W][S::RS];
     double xchg[2 * W * 64];
+    alignas(16) double wb[W][S::BCE];
     int go;
 };
 
@@ -359,7 +429,8 @@ template <int N, int W = 8> __host__ __device__ constexpr int coop_group(int gro
 // (WA = the fewest that hold them, a power of two): idle waves only match the
 // per-step barriers, so a small group runs at the speed of a small workgroup.
 template <int N, int W, int WA>
-__device__ __forceinline__ void coop_factor(const double* src, int rows, double* Rl, double* xchg, int wv, int L) {
+__device__ __forceinline__ void coop_factor(const double* src, int rows, double* Rl, double* xchg, double* wb, int wv,
+                                            int L) {
     using CT = CoopTree<N, W>;
     using S = Small<double, double, N, CT::RPL>;
     if (wv < WA) {
@@ -372,7 +443,7 @@ __device__ __forceinline__ void coop_factor(const double* src, int rows, double*
 #pragma unroll
             for (int c = 0; c < N; ++c) x[r][c] = ok ? rowp[c] : 0.0;
         }
-        S::template step<0, WA>(x, Rl, xchg);
+        S::template step<0, WA, false>(x, Rl, xchg, wb);
     } else if constexpr (WA > 1) {
         for (int j = 0; j < N; ++j) __syncthreads();   // one barrier per step of the active waves
     }
@@ -401,10 +472,11 @@ __device__ __forceinline__ void coop_tree_run(const TreeArgs& t, int64_t group0,
         wave_lds_sync();
         const double* src = t.nodes + (base + first) * NN;    // stacked rows, n wide
         const int need = (rows + 64 * CT::RPL - 1) / (64 * CT::RPL);
-        if (need <= 1) coop_factor<N, W, 1>(src, rows, Rl, xchg, wv, L);
-        else if (W >= 2 && need <= 2) coop_factor<N, W, (W >= 2 ? 2 : 1)>(src, rows, Rl, xchg, wv, L);
-        else if (W >= 4 && need <= 4) coop_factor<N, W, (W >= 4 ? 4 : 1)>(src, rows, Rl, xchg, wv, L);
-        else coop_factor<N, W, W>(src, rows, Rl, xchg, wv, L);
+        double* wb = lds.wb[wv];
+        if (need <= 1) coop_factor<N, W, 1>(src, rows, Rl, xchg, wb, wv, L);
+        else if (W >= 2 && need <= 2) coop_factor<N, W, (W >= 2 ? 2 : 1)>(src, rows, Rl, xchg, wb, wv, L);
+        else if (W >= 4 && need <= 4) coop_factor<N, W, (W >= 4 ? 4 : 1)>(src, rows, Rl, xchg, wb, wv, L);
+        else coop_factor<N, W, W>(src, rows, Rl, xchg, wb, wv, L);
         wave_lds_sync();
         double cs = 0.0;
         if (wv == 0 && L < N) {

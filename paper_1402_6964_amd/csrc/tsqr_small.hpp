@@ -377,7 +377,7 @@ __device__ __forceinline__ void small_slab(const StreamArgs& a, int64_t sid, uns
 }
 
 template <typename T, typename TI, int N, int RPL, int LOAD>
-__global__ void __launch_bounds__(256) tsqr_small_kernel(StreamArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) tsqr_small_kernel(StreamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wv = (int)(threadIdx.x >> 6);
     const int64_t sid = (int64_t)blockIdx.x * 4 + wv;

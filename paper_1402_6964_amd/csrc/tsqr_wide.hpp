@@ -178,6 +178,9 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
             }
             acc += (double)butterfly<P>(p);
         }
+        // Step 0 of this block reuses the pivot and scalar slots of parity 0,
+        // which the previous block's step n - 1 (n odd) may still be reading.
+        if (b0 != r0) __syncthreads();
         int off = 0;                                 // start of row j in this wave's storage
         Wide<T, TI, NW, W, RPL>::template level<0>(x, n, wv, L, Rw, apub, pv, off);
     }

@@ -74,13 +74,27 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                     for (int r = 1; r < RPL; ++r) sg = fma_t(x[r][Q], x[r][Q], sg);
                     const double sigma = (double)wave_sum(sg);
                     const double alpha = Rw[off];    // R(j, j): first entry of the owner's row j
-                    const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
                     const bool lv = sigma != 0.0;
-                    const double beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-                    const double inv_beta = rcp_fast<double>(beta);
+                    double beta, inv_beta, s_;
+                    if constexpr (sizeof(T) == 4) {
+                        // FP32 block: a live sigma is a nonzero FP32 value, so
+                        // alpha^2 + sigma and beta (alpha - beta) are normal
+                        // FP64 numbers; one reciprocal gives both scalars.
+                        const double nrm = sqrt_normal(__builtin_fma(alpha, alpha, sigma));
+                        beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+                        const double amb = alpha - beta;
+                        const double q = rcp_fast<double>(beta * amb);         // unused unless live
+                        inv_beta = amb * q;
+                        s_ = beta * q;
+                    } else {
+                        const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
+                        beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
+                        inv_beta = rcp_fast<double>(beta);
+                        s_ = rcp_fast<double>(alpha - beta);
+                    }
                     if (L == 0) {
                         sc[0] = beta;
-                        sc[1] = lv ? rcp_fast<double>(alpha - beta) : 0.0;   // s = 1 / (alpha - beta)
+                        sc[1] = lv ? s_ : 0.0;                               // s = 1 / (alpha - beta)
                         sc[2] = lv ? (beta - alpha) * inv_beta : 0.0;        // tau
                         sc[3] = lv ? inv_beta : 0.0;                         // 1 / beta for the block update
                     }

@@ -13,7 +13,8 @@
 //     B(:, k) <- B(:, k) + (1 / beta) B(:, j) w_k  (since tau / (alpha - beta) = -1 / beta).
 // All d_k of one step come from one reduce-scatter butterfly (wave.hpp), so
 // value k - j of step j lives in a fixed lane pattern; row j of R is stored in
-// LDS indexed by that value number, so the R update is one lane-parallel op.
+// LDS indexed by that value number, so the R update is one lane-parallel op,
+// and the w_k reach every lane through a small LDS slot per wave.
 // The block's l1 column sums (Sec. 3.3) are reduced by one more butterfly and
 // accumulated in FP64.
 //

@@ -178,6 +178,31 @@ def test_kronecker_full_size(lib):
     assert np.abs(csg - np.kron(dA, dA)).max() / np.kron(dA, dA).max() <= 1e-6
 
 
+@pytest.mark.parametrize("n,dt", [(25, torch.float32), (2, torch.float32), (40, torch.float32), (20, torch.float64)])
+def test_more_than_2_31_elements(lib, n, dt):
+    """Row-major inputs with more than 2^31 elements (64-bit row offsets in the
+    staged and wide leaves): t stacked copies of a block A give R = sqrt(t) R_A
+    and colsum = t d_A, with R_A and d_A from the oracle on A alone."""
+    elems = (1 << 31) + (1 << 27)
+    mA = 50_000
+    t = -(-elems // (mA * n))
+    A = synth.random_matrix(mA, n, dtype=dt, seed_tag=27, dist="lognormal")
+    X = A.cuda().repeat(t, 1)
+    assert X.numel() > (1 << 31)
+    Rg, csg = _run(lib, X)
+    del X
+    torch.cuda.empty_cache()
+    Ah = A.numpy().astype(np.float64)
+    ref = np.sqrt(t) * otsqr.tsqr_r_final(Ah, leaf_rows=5000)
+    f32 = dt == torch.float32
+    gram = np.linalg.norm(Rg.T @ Rg - ref.T @ ref) / np.linalg.norm(ref) ** 2
+    assert gram <= (1e-6 if f32 else 1e-12), f"gram error {gram:.3e}"
+    cn = np.linalg.norm(ref, axis=0)
+    assert np.max(np.abs(np.linalg.norm(Rg, axis=0) - cn) / cn) <= (1e-5 if f32 else 1e-12)
+    dA = np.abs(Ah).sum(0)
+    assert np.max(np.abs(csg - t * dA) / (t * dA)) <= (1e-6 if f32 else 1e-13)
+
+
 def test_invalid_arguments(lib):
     X = torch.zeros((10, 4), dtype=torch.float32, device="cuda")
     R = torch.empty((4, 4), dtype=torch.float64, device="cuda")

@@ -36,8 +36,8 @@ enum : int { CLS_NONE = -1, CLS_S16 = 0, CLS_S32 = 1, CLS_W64 = 2, CLS_W128 = 3 
 constexpr int kWaves = 8;                                   // waves per workgroup
 constexpr int kRplS16 = 8;        // one-wave classes: 512- and 256-row blocks
 constexpr int kRplS32 = 4;
-constexpr int kRplW64 = 16;       // 8 columns per wave
-constexpr int kRplW128 = 8;       // 16 columns per wave
+constexpr int kRplW64 = 24;       // 8 columns per wave
+constexpr int kRplW128 = 12;      // 16 columns per wave
 constexpr int kRplM64 = 8;        // FP64 merges, 8 columns per wave
 constexpr int kRplM128 = 4;       // FP64 merges, 16 columns per wave
 using S16 = Small<float, float, 16, kRplS16>;
@@ -70,7 +70,7 @@ __host__ __device__ constexpr int64_t class_block(int c) {
     return c == CLS_S16 ? S16::BR : c == CLS_S32 ? S32::BR : c == CLS_W64 ? W64::BR : W128::BR;
 }
 __host__ __device__ constexpr int64_t class_slab(int c) {
-    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4096 : c == CLS_W64 ? 8192 : 16384;
+    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4096 : c == CLS_W64 ? 7680 : 16128;
 }
 // Nodes per tree group.  For the one-wave classes a group must hold whole
 // items (multiples of kWaves slabs); 24 and 16 are near the fastest pass sizes.

@@ -21,6 +21,9 @@ hipError_t launch_wide_f64_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f64_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32_rowbuf(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f64_rowbuf(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32w_rowbuf(const WideArgs& a, hipStream_t s);
 int rows_per_lane_f32(int n, bool staged);
 int rows_per_lane_f64(int n, bool staged);
 
@@ -47,11 +50,14 @@ hipError_t launch_leaf(Path p, int load, int n, const StreamArgs& a, hipStream_t
 }
 
 hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
-    const bool col = load == LOAD_COL;
+    const bool col = load == LOAD_COL, buf = load == LOAD_ROW_BUF;
     switch (p) {
-        case Path::F32: return col ? launch_wide_f32_col(a, s) : launch_wide_f32_row(a, s);
-        case Path::F64: return col ? launch_wide_f64_col(a, s) : launch_wide_f64_row(a, s);
-        case Path::F32W: return col ? launch_wide_f32w_col(a, s) : launch_wide_f32w_row(a, s);
+        case Path::F32:
+            return col ? launch_wide_f32_col(a, s) : buf ? launch_wide_f32_rowbuf(a, s) : launch_wide_f32_row(a, s);
+        case Path::F64:
+            return col ? launch_wide_f64_col(a, s) : buf ? launch_wide_f64_rowbuf(a, s) : launch_wide_f64_row(a, s);
+        case Path::F32W:
+            return col ? launch_wide_f32w_col(a, s) : buf ? launch_wide_f32w_rowbuf(a, s) : launch_wide_f32w_row(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -80,7 +86,17 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     // (8 columns x 16 rows per lane), else 4 (16 columns per wave)
     const bool f32_8x8 = p.path == Path::F32 && n <= 64 && col;
     p.waves = !p.wide ? 1 : (n > 64 || f32_8x8 ? 8 : 4);
-    const int rpl = p.wide ? (p.path == Path::F32 ? (f32_8x8 ? 16 : 8) : 4)
+    // wide row-major input goes through buffer resources when a block's row
+    // offsets fit their 32 bits (FP32 above 64 columns: 11 rows per lane;
+    // FP64 blocks: 5, else 4); FP32 up to 64 columns keeps per-element loads
+    // with 12 rows per lane
+    const int64_t esize = dt == TSNMF_F64 ? 8 : 4;
+    const bool f32 = p.path == Path::F32;
+    const int rpl_buf = f32 ? 11 : 5;
+    if (p.wide && p.load == LOAD_ROW && !(f32 && n <= 64) && 64LL * rpl_buf * ld * esize < ((int64_t)1 << 31))
+        p.load = LOAD_ROW_BUF;
+    const int rpl = p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
+                              : f32 ? (f32_8x8 ? 20 : (n <= 64 && !col ? 12 : 11)) : 4)
                            : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
                                                   : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
     p.block_rows = 64LL * rpl;

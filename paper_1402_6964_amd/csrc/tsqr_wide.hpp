@@ -18,6 +18,10 @@
 
 namespace tsnmf {
 
+// Row-major loads through a buffer resource over each block's rows (wide
+// kernels only; needs 64 RPL ld sizeof(TI) < 2^31).
+constexpr int LOAD_ROW_BUF = 3;
+
 struct WideArgs {
     const void* X;
     int64_t m;
@@ -151,7 +155,10 @@ template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
 __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsigned char* smem) {
     using S = Wide<T, TI, NW, W, RPL>;
     constexpr int P = S::P;
-    const int wv = (int)(threadIdx.x >> 6);
+    // The wave index is uniform across the wave; reading it through
+    // readfirstlane keeps it, the R base and the owner tests in scalar
+    // registers.
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int L = lane_id();
     const int n = a.n;
     double* Rw = (double*)smem + (size_t)wv * S::RW;  // this wave's part of R (compact rows)
@@ -167,18 +174,49 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     __syncthreads();
     for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
         T x[RPL][NW];
+        if constexpr (LOAD == LOAD_ROW_BUF) {
+            // Row-major block through a buffer resource over its rows (the
+            // caller keeps BR ld sizeof(TI) below 2^31): the column offset of
+            // each load is a scalar (this wave's column k), the row offset
+            // one register per row, and rows past r1 read as zero.  No
+            // address arithmetic per element, so the loads of a block issue
+            // back to back.
+            const int64_t nrow = min((int64_t)S::BR, r1 - b0);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(X + b0 * a.ld), 0, (int)(nrow * a.ld * (int64_t)sizeof(TI)), 0x00020000);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int64_t i = b0 + r * 64 + L;
-            const bool ok = i < r1;
+            for (int r = 0; r < RPL; ++r) {
+                const int vo = (r * 64 + L) * (int)a.ld * (int)sizeof(TI);
 #pragma unroll
-            for (int c = 0; c < NW; ++c) {
-                const int k = wv + W * c;
-                const bool okc = ok && k < n;
-                const TI* p = LOAD == LOAD_COL ? X + min(i, a.m - 1) + (int64_t)min(k, n - 1) * a.ld
-                                               : X + min(i, a.m - 1) * a.ld + min(k, n - 1);
-                const TI v = LOAD == LOAD_COL ? __builtin_nontemporal_load(p) : *p;
-                x[r][c] = okc ? (T)v : T(0);
+                for (int c = 0; c < NW; ++c) {
+                    const int k = wv + W * c;
+                    const int so = min(k, n - 1) * (int)sizeof(TI);
+                    TI v;
+                    if constexpr (sizeof(TI) == 4)
+                        v = __builtin_bit_cast(TI, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0));
+                    else
+                        v = __builtin_bit_cast(TI, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+                    x[r][c] = k < n ? (T)v : T(0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t i = b0 + r * 64 + L;
+                const bool ok = i < r1;
+#pragma unroll
+                for (int c = 0; c < NW; ++c) {
+                    // column-major loads take the wave index in its vector
+                    // form: with a scalar column offset the compiler
+                    // serialises them (one address pair reused, a full wait
+                    // per load)
+                    const int k = (LOAD == LOAD_COL ? (int)(threadIdx.x >> 6) : wv) + W * c;
+                    const bool okc = ok && k < n;
+                    const TI* p = LOAD == LOAD_COL ? X + min(i, a.m - 1) + (int64_t)min(k, n - 1) * a.ld
+                                                   : X + min(i, a.m - 1) * a.ld + min(k, n - 1);
+                    const TI v = LOAD == LOAD_COL ? __builtin_nontemporal_load(p) : *p;
+                    x[r][c] = okc ? (T)v : T(0);
+                }
             }
         }
         {   // l1 column sums of the block, own columns
@@ -217,7 +255,7 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
 }
 
 template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
-__global__ void __launch_bounds__(W * 64) tsqr_wide_kernel(WideArgs a) {
+__global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2))) tsqr_wide_kernel(WideArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     wide_slab<T, TI, NW, W, RPL, LOAD>(a, blockIdx.x, smem);
 }
@@ -251,7 +289,7 @@ __device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t
         a.tree = t;
         a.tree.nodes = t.nodes + (nbase + group) * nn;
         a.tree.node_cs = nullptr;
-        wide_slab<double, double, NW, W, RPLD, LOAD_ROW>(a, 0, smem);
+        wide_slab<double, double, NW, W, RPLD, LOAD_ROW_BUF>(a, 0, smem);
         double* cs_out = t.node_cs + (nbase + group) * n;
         for (int c = tid; c < n; c += W * 64) {
             double s = 0.0;

@@ -7,7 +7,7 @@ namespace tsnmf {
 // per lane for up to 64 columns (5e7 x 64: 13.9 -> 12.8 ms).  Row-major
 // blocks are read row by row by every wave, which favours fewer waves.
 hipError_t launch_wide_f32_col(const WideArgs& a, hipStream_t stream) {
-    if (a.n <= 64) return launch_wide_w<float, float, 8, LOAD_COL, 8, 16>(a, stream);
+    if (a.n <= 64) return launch_wide_w<float, float, 8, LOAD_COL, 8, 20>(a, stream);
     return launch_wide_w<float, float, 8, LOAD_COL>(a, stream);
 }
 }  // namespace tsnmf

@@ -12,7 +12,7 @@ namespace tsnmf {
 // as many rows per lane as 128 block registers hold: fewer columns per wave
 // mean a shorter butterfly per step and more rows to spread each step's fixed
 // cost (reflector scalars, pivot exchange, barrier) over.
-template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 8 : 4; }
+template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 11 : 5; }
 
 template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_rpl<T>()>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {

@@ -99,8 +99,9 @@ int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags
 
 /* Launch geometry of the TSQR path.  Zero fields mean "library default". */
 typedef struct tsnmf_tsqr_config {
-    int64_t leaf_rows;      /* rows per workgroup slab (the TSQR leaf); rounded up
-                               to a whole number of row blocks                    */
+    int64_t leaf_rows;      /* rows per slab (the TSQR leaf); a slab that is not
+                               a whole number of row blocks ends in a partial
+                               block, padded with zero rows                     */
     int32_t tree_arity;     /* slab factors merged per tree node, 2..64 (2 = a
                                binary tree); n <= 32 only, capped at the most
                                stacked rows one workgroup pass holds; the wider

@@ -262,6 +262,23 @@ def test_wide_rowmajor_strided(lib, n, dt):
                           1e-6 if f32 else 1e-13, norm_tol=1e-5 if f32 else 1e-12)
 
 
+@pytest.mark.parametrize("n,dt", [(100, torch.float32), (70, torch.float64), (40, torch.float64)])
+def test_wide_rowmajor_huge_stride(lib, n, dt):
+    """Row stride so large (ld = 900,000) that a block's row offsets leave the
+    32-bit range of a buffer resource: the wide leaf falls back to
+    per-element 64-bit addresses."""
+    m, ld = 2_500, 900_000
+    X = synth.random_matrix(m, n, dtype=dt, seed_tag=28, dist="uniform")
+    store = torch.zeros((m, ld), dtype=dt, device="cuda")
+    store[:, :n] = X.cuda()
+    Rg, csg = _run(lib, store[:, :n])
+    del store
+    torch.cuda.empty_cache()
+    f32 = dt == torch.float32
+    _check_against_oracle(Rg, csg, X.numpy(), 1e-6 if f32 else 1e-12, 5e-5 if f32 else 1e-10,
+                          1e-6 if f32 else 1e-13, norm_tol=1e-5 if f32 else 1e-12)
+
+
 @pytest.mark.parametrize("m,n", [(1, 33), (40, 64), (65, 70), (129, 128), (1000, 40)])
 def test_wide_short_inputs(lib, m, n):
     """Fewer rows than one 64-row chunk, one chunk plus a ragged tail, and

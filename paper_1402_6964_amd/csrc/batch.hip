@@ -34,6 +34,11 @@ namespace {
 enum : int { CLS_NONE = -1, CLS_S16 = 0, CLS_S32 = 1, CLS_W64 = 2, CLS_W128 = 3 };
 
 constexpr int kWaves = 8;                                   // waves per workgroup
+// The 128-column class reads 64-row chunks through buffer resources with
+// 32-bit offsets: 64 ld 4 bytes must stay below 2^31 (measured against
+// per-element loads: 71.4 -> 69.3 ms on the 512-matrix workload; the
+// 64-column class keeps per-element loads, which measured faster there).
+constexpr int64_t kMaxBatchLd = (int64_t)1 << 23;
 constexpr int kRplS16 = 8;        // one-wave classes: 512- and 256-row blocks
 constexpr int kRplS32 = 4;
 constexpr int kRplW64 = 24;       // 8 columns per wave
@@ -161,7 +166,8 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
     // 1. validity and cost; invalid matrices get NaN outputs when their R fits
     for (int i = t; i < B; i += kPlanThreads) {
         const int64_t mi = m[i], ni = n[i], li = ld[i];
-        const bool ok = X[i] != nullptr && R[i] != nullptr && ni >= 1 && ni <= TSNMF_MAX_N && mi >= 1 && li >= ni;
+        const bool ok = X[i] != nullptr && R[i] != nullptr && ni >= 1 && ni <= TSNMF_MAX_N && mi >= 1 && li >= ni &&
+                        (ni <= 64 || li < kMaxBatchLd);
         cost[i] = ok ? (float)mi * (float)(ni * ni) : -1.0f;
         if (!ok && R[i] != nullptr && ni >= 1 && ni <= TSNMF_MAX_N) {
             const double nan = __builtin_nan("");
@@ -317,7 +323,7 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
         } else {
             const WideArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.n, 0, M.tree};
             if (cls == CLS_W64) wide_slab<float, float, 8, kWaves, kRplW64, LOAD_ROW>(a, s0, smem);
-            else wide_slab<float, float, 16, kWaves, kRplW128, LOAD_ROW>(a, s0, smem);
+            else wide_slab<float, float, 16, kWaves, kRplW128, LOAD_ROW_BUF>(a, s0, smem);
         }
         // slab group ticket: every wave releases its node stores first
         grid_release();
@@ -453,7 +459,8 @@ int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const i
         TSNMF_HIP(hipStreamSynchronize(stream));
         int64_t w = 0, k = 0;
         for (int i = 0; i < B; ++i) {
-            if (hn[i] < 1 || hn[i] > TSNMF_MAX_N || hm[i] < 1 || hl[i] < hn[i]) continue;
+            if (hn[i] < 1 || hn[i] > TSNMF_MAX_N || hm[i] < 1 || hl[i] < hn[i] || (hn[i] > 64 && hl[i] >= kMaxBatchLd))
+                continue;
             const Sizes s = matrix_sizes(hm[i], hn[i], class_of(hn[i], hl[i]), 0);
             w += s.words;
             k += s.tickets;

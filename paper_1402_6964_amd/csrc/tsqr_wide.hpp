@@ -18,8 +18,8 @@
 
 namespace tsnmf {
 
-// Row-major loads through a buffer resource over each block's rows (wide
-// kernels only; needs 64 RPL ld sizeof(TI) < 2^31).
+// Row-major loads through a buffer resource per 64-row chunk (wide kernels
+// only; needs 64 ld sizeof(TI) < 2^31).
 constexpr int LOAD_ROW_BUF = 3;
 
 struct WideArgs {
@@ -175,18 +175,19 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     for (int64_t b0 = r0; b0 < r1; b0 += S::BR) {
         T x[RPL][NW];
         if constexpr (LOAD == LOAD_ROW_BUF) {
-            // Row-major block through a buffer resource over its rows (the
-            // caller keeps BR ld sizeof(TI) below 2^31): the column offset of
-            // each load is a scalar (this wave's column k), the row offset
-            // one register per row, and rows past r1 read as zero.  No
-            // address arithmetic per element, so the loads of a block issue
-            // back to back.
-            const int64_t nrow = min((int64_t)S::BR, r1 - b0);
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(X + b0 * a.ld), 0, (int)(nrow * a.ld * (int64_t)sizeof(TI)), 0x00020000);
+            // Row-major rows through one buffer resource per 64-row chunk
+            // (the caller keeps 64 ld sizeof(TI) below 2^31): the column
+            // offset of each load is a scalar (this wave's column k), the row
+            // offset is the same register for every chunk, and rows past r1
+            // read as zero.  No address arithmetic per element, so the loads
+            // of a block issue back to back.
+            const int vo = L * (int)a.ld * (int)sizeof(TI);
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                const int vo = (r * 64 + L) * (int)a.ld * (int)sizeof(TI);
+                const int64_t c0 = b0 + r * 64;
+                const int nr = (int)max((int64_t)0, min((int64_t)64, r1 - c0));
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(X + c0 * a.ld), 0, nr * (int)a.ld * (int)sizeof(TI), 0x00020000);
 #pragma unroll
                 for (int c = 0; c < NW; ++c) {
                     const int k = wv + W * c;

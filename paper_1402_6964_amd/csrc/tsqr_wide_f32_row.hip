@@ -8,7 +8,7 @@ hipError_t launch_wide_f32_row(const WideArgs& a, hipStream_t stream) {
     if (a.n <= 64) return launch_wide_w<float, float, 4, LOAD_ROW, 16, 12>(a, stream);
     return launch_wide_w<float, float, 8, LOAD_ROW>(a, stream);
 }
-// Rows through a buffer resource (64 RPL ld sizeof(TI) < 2^31).
+// Rows through a buffer resource per 64-row chunk (64 ld sizeof(TI) < 2^31).
 hipError_t launch_wide_f32_rowbuf(const WideArgs& a, hipStream_t stream) {
     if (a.n <= 64) return launch_wide_f32_row(a, stream);
     return launch_wide_w<float, float, 8, LOAD_ROW_BUF>(a, stream);

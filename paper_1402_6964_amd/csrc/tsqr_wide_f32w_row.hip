@@ -6,7 +6,7 @@ hipError_t launch_wide_f32w_row(const WideArgs& a, hipStream_t stream) {
     if (a.n <= 64) return launch_wide_w<double, float, 4, LOAD_ROW, 16, 4>(a, stream);
     return launch_wide_w<double, float, 8, LOAD_ROW, 16, 4>(a, stream);
 }
-// Rows through a buffer resource (64 RPL ld sizeof(TI) < 2^31).
+// Rows through a buffer resource per 64-row chunk (64 ld sizeof(TI) < 2^31).
 hipError_t launch_wide_f32w_rowbuf(const WideArgs& a, hipStream_t stream) {
     if (a.n <= 64) return launch_wide_w<double, float, 4, LOAD_ROW_BUF>(a, stream);
     return launch_wide_w<double, float, 8, LOAD_ROW_BUF>(a, stream);

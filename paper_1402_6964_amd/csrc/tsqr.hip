@@ -87,13 +87,13 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     const bool f32_8x8 = p.path == Path::F32 && n <= 64 && col;
     p.waves = !p.wide ? 1 : (n > 64 || f32_8x8 ? 8 : 4);
     // wide row-major input goes through buffer resources when the row offsets
-    // of a 64-row chunk fit their 32 bits (FP32 above 64 columns: 11 rows per
-    // lane; FP64 blocks: 5, else 4); FP32 up to 64 columns keeps per-element
-    // loads with 12 rows per lane
+    // of a 64-row chunk fit their 32 bits (FP32 blocks: 12 rows per lane;
+    // FP64 blocks: 5); otherwise per-element loads (FP32: 12 up to 64
+    // columns, else 11; FP64: 4)
     const int64_t esize = dt == TSNMF_F64 ? 8 : 4;
     const bool f32 = p.path == Path::F32;
-    const int rpl_buf = f32 ? 11 : 5;
-    if (p.wide && p.load == LOAD_ROW && !(f32 && n <= 64) && 64LL * ld * esize < ((int64_t)1 << 31))
+    const int rpl_buf = f32 ? 12 : 5;
+    if (p.wide && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
     const int rpl = p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
                               : f32 ? (f32_8x8 ? 20 : (n <= 64 && !col ? 12 : 11)) : 4)

@@ -96,7 +96,7 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     if (p.wide && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
     const int rpl = p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
-                              : f32 ? (f32_8x8 ? 20 : (n <= 64 && !col ? 12 : 11)) : 4)
+                              : f32 ? (f32_8x8 ? 22 : (n <= 64 && !col ? 12 : 11)) : 4)
                            : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
                                                   : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
     p.block_rows = 64LL * rpl;

@@ -39,8 +39,8 @@ constexpr int kWaves = 8;                                   // waves per workgro
 // per-element loads: 71.4 -> 69.3 ms on the 512-matrix workload; the
 // 64-column class keeps per-element loads, which measured faster there).
 constexpr int64_t kMaxBatchLd = (int64_t)1 << 23;
-constexpr int kRplS16 = 8;        // one-wave classes: 512- and 256-row blocks
-constexpr int kRplS32 = 4;
+constexpr int kRplS16 = 8;        // one-wave classes: 512- and 320-row blocks
+constexpr int kRplS32 = 5;
 constexpr int kRplW64 = 24;       // 8 columns per wave
 constexpr int kRplW128 = 12;      // 16 columns per wave
 constexpr int kRplM64 = 8;        // FP64 merges, 8 columns per wave

@@ -13,8 +13,10 @@ divided by the mean step time).  The line also carries:
                 on the launch stream during the timed steps, against the
                 78.6 TF/s FP32 vector peak without packed instructions (the
                 kernel's bound); its bytes against 8 TB/s ride along;
-  cpu_baseline  the CPU oracle (plain FP64 numpy Householder TSQR) timed on a
-                bounded row sample of the same X on this host;
+  cpu_baseline  the CPU oracle (plain FP64 numpy Householder TSQR) timed on
+                this host: over all of X on up to 16 worker processes (the
+                host's CPU count is recorded), and on one thread over a
+                bounded row sample;
   r_error       ||R^T R - X^T X||_F / ||X||_F^2 and the column-norm error of
                 the benchmarked R against the oracle's reference sums of X;
   extras        the other hot-path workloads, each timed after the main steps
@@ -84,14 +86,29 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(X_gpu, R_gpu, cs_gpu, target_s):
-    """Oracle timed on a bounded sample; R error of the benchmarked R."""
+def cpu_baseline(X_gpu, R_gpu, cs_gpu, target_s, pool):
+    """Oracle timed on the host: on all worker cores over the whole input, and
+    on one thread over a bounded sample; R error of the benchmarked R."""
     import numpy as np
     import threadpoolctl
+    from oracle import parallel as opar
     from oracle import tsqr as otsqr
 
     out = {}
     m, n = X_gpu.shape
+    X = X_gpu.cpu().numpy()
+    all_cores = None
+    if pool is not None:
+        pool.load(X)
+        t0 = time.perf_counter()
+        pool.tsqr_r(1000)
+        t_all = time.perf_counter() - t0
+        all_cores = {"value": m * n * 4 / t_all / 1e9, "unit": "GB/s", "cores": pool.workers,
+                     "kind": "oracle",
+                     "sample": f"all {m} x {n} FP32 rows, FP64 numpy Householder leaves of 1000 rows + binary "
+                               f"tree (aligned runs of leaves in {pool.workers} worker processes, the top of "
+                               f"the tree in the parent; the same R bit for bit), {t_all:.1f} s"}
+        pool.close()
     with threadpoolctl.threadpool_limits(1):
         # calibrate on a small sample, then time a sample sized for ~target_s
         rows = 20_000
@@ -105,12 +122,15 @@ def cpu_baseline(X_gpu, R_gpu, cs_gpu, target_s):
         t0 = time.perf_counter()
         otsqr.tsqr_r_final(Xs, leaf_rows=1000)
         t = time.perf_counter() - t0
-    out["cpu_baseline"] = {
+    single = {
         "value": rows * n * 4 / t / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
         "sample": f"first {rows} rows of the {m} x {n} FP32 input, FP64 numpy Householder leaves "
                   f"of 1000 rows + binary tree, {t:.1f} s, one thread"}
+    if all_cores is not None:
+        out["cpu_baseline"] = {**all_cores, "host_cores": opar.host_cores(), "single_thread": single}
+    else:
+        out["cpu_baseline"] = {**single, "host_cores": opar.host_cores()}
     # R error of the benchmarked R against the oracle's reference sums of all of X
-    X = X_gpu.cpu().numpy()
     colsum, colsq, gram = otsqr.reference_sums(X)
     R = R_gpu.cpu().numpy()
     cs = cs_gpu.cpu().numpy()
@@ -284,6 +304,13 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
+    # the all-core oracle's worker processes start before this process
+    # touches the GPU (spawned, they never do); the box grants one GPU's share
+    # of its CPUs, 16
+    pool = None
+    if not args.no_cpu and not args.copy_reference:
+        from oracle import parallel as opar
+        pool = opar.OraclePool(max(1, min(16, opar.host_cores())))
     import torch
     from paper_1402_6964_amd import synth, tsnmf
 
@@ -378,7 +405,7 @@ def main():
     if not args.no_cpu:
         torch.cuda.synchronize()
         _note("cpu baseline: timing the oracle")
-        line.update(cpu_baseline(X, tsnmf.colmajor_square(Rbuf), cs, args.cpu_seconds))
+        line.update(cpu_baseline(X, tsnmf.colmajor_square(Rbuf), cs, args.cpu_seconds, pool))
     if not args.no_extras:
         del X, d
         torch.cuda.empty_cache()

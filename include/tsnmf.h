@@ -28,7 +28,11 @@
  *   - The library keeps one grow-only device workspace per device.  It is
  *     allocated on first use (or by tsnmf_reserve); a call made while `stream`
  *     is being captured into a graph returns TSNMF_ERR_CAPTURE instead of
- *     allocating, so reserve before capturing.
+ *     allocating, so reserve before capturing.  When a later call (or a
+ *     larger reserve) grows the workspace, the old buffer is retired, not
+ *     freed: graphs captured earlier keep naming it in their kernel
+ *     arguments and stay valid to replay.  tsnmf_workspace_release() frees
+ *     the retired buffers once no such graph will be replayed.
  *   - Calls that share the workspace must not run concurrently on different
  *     streams of the same device.
  */
@@ -195,7 +199,8 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
  * M diag(1/colscale): r times pick j* = argmax_j ||Z(:, j)||_2^2 over columns
  * not yet picked (ties -> smallest j), then Z <- Z - u (u^T Z) with
  * u = Z(:, j*) / ||Z(:, j*)||.  Z starts as M diag(1/colscale).
- *   M         device FP64, p x n column-major (ldm >= p), p and n in 1..256
+ *   M         device FP64, p x n column-major (ldm >= p), p in 1..4096 (R,
+ *             or the k x n projection G^T X of Sec. 2.3), n in 1..256
  *   colscale  device FP64[n] or NULL (no scaling); e.g. the colsum of tsnmf_tsqr_r
  *   r         1..n picks
  *   K         device int32[r] output, in selection order
@@ -214,7 +219,7 @@ int tsnmf_select_spa(const double* M, int32_t p, int32_t n, int32_t ldm,
  * j* = argmax_j ||Res^T M(:, j)||_2 / ||M(:, j)||_2 over unpicked nonzero
  * columns, then Res = M - M(:, K) H with H the NNLS fit of every column of M on
  * the picked columns (Lawson-Hanson, as tsnmf_nnls).  Res starts as M.
- *   M, p, n, ldm as in tsnmf_select_spa;  r in 1..min(n, 64)
+ *   M, p, n, ldm as in tsnmf_select_spa but p <= 256;  r in 1..min(n, 64)
  *   K     device int32[r] output in selection order (-1 past an early stop)
  *   info  device int32[1] output: number picked
  */
@@ -259,9 +264,17 @@ int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int
 /* ---- housekeeping ------------------------------------------------------------------- */
 
 /* Grow the current device's workspace so that TSQR calls with m <= max_m and
-   n <= max_n, and projections with k <= max_k, need no allocation (required
-   before graph capture).  Host call, synchronous. */
+   n <= max_n (any dtype, layout, leaf precision and row stride, default
+   geometry or a tuned entry; an explicit tsnmf_tsqr_config.leaf_rows that
+   makes more than 2048 slabs may need more), and projections with
+   k <= max_k, need no allocation (required before graph capture).  Host
+   call, synchronous. */
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
+
+/* Free the workspace buffers that growth has retired on the current device
+   (single-call and batched), after waiting for the device.  Graphs captured
+   before that growth must not be replayed afterwards.  Host call. */
+int tsnmf_workspace_release(void);
 
 /* Profiling aid.  While enabled, TSQR and projection calls record HIP
    events on their stream around their main kernel ("stage 0": the leaf /

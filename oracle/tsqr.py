@@ -70,8 +70,20 @@ def tsqr_r(X, leaf_rows=1000):
     m, n = X.shape
     if m < 1 or n < 1:
         raise ValueError("empty matrix")
-    level = [householder_r(np.asarray(X[i:i + leaf_rows], dtype=np.float64))
-             for i in range(0, m, leaf_rows)]
+    return reduce_tree(leaf_factors(X, leaf_rows))
+
+
+def leaf_factors(X, leaf_rows):
+    """The leaf step: the R of every row block of height ``leaf_rows``."""
+    X = np.asarray(X)
+    return [householder_r(np.asarray(X[i:i + leaf_rows], dtype=np.float64))
+            for i in range(0, X.shape[0], leaf_rows)]
+
+
+def reduce_tree(level):
+    """The binary tree: pairs (0, 1), (2, 3), ... of a level are replaced by the
+    R of their stacked 2n x n matrix; an odd last factor moves up unchanged."""
+    level = list(level)
     while len(level) > 1:
         nxt = []
         for t in range(0, len(level) - 1, 2):

@@ -12,6 +12,10 @@ thread_local int g_last_hip = 0;
 struct Workspace {
     void* ptr = nullptr;
     size_t bytes = 0;
+    // Buffers replaced by a larger one.  A graph captured before the growth
+    // still names them in its kernel arguments, so they are kept until
+    // tsnmf_workspace_release() (or the end of the process).
+    std::vector<void*> retired;
 };
 std::mutex g_ws_mu;
 std::vector<Workspace> g_ws;
@@ -25,14 +29,10 @@ bool is_capturing(hipStream_t s) {
 int grow(int dev, size_t bytes) {
     Workspace& w = g_ws[dev];
     if (w.bytes >= bytes) return TSNMF_OK;
-    // The old buffer may still be in use by enqueued work: drain the device first.
-    if (w.ptr != nullptr) {
-        TSNMF_HIP(hipDeviceSynchronize());
-        TSNMF_HIP(hipFree(w.ptr));
-        w.ptr = nullptr;
-        w.bytes = 0;
-    }
+    // Growth by at least half the current size keeps the retired buffers
+    // below twice the live one.
     size_t sz = bytes < ((size_t)1 << 20) ? ((size_t)1 << 20) : bytes;
+    if (sz < w.bytes + w.bytes / 2) sz = w.bytes + w.bytes / 2;
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, sz);
     if (e != hipSuccess) {
@@ -45,6 +45,9 @@ int grow(int dev, size_t bytes) {
         (void)hipFree(p);
         return hip_fail(e);
     }
+    // The old buffer may still be in use by enqueued work or by a captured
+    // graph: retire it instead of freeing it.
+    if (w.ptr != nullptr) w.retired.push_back(w.ptr);
     w.ptr = p;
     w.bytes = sz;
     return TSNMF_OK;
@@ -119,6 +122,17 @@ int workspace_get(size_t bytes, hipStream_t stream, void** out) {
         if (int st = grow(dev, bytes)) return st;
     }
     *out = g_ws[dev].ptr;
+    return TSNMF_OK;
+}
+
+int workspace_release_retired() {
+    int dev = 0;
+    TSNMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev || g_ws[dev].retired.empty()) return TSNMF_OK;
+    TSNMF_HIP(hipDeviceSynchronize());
+    for (void* q : g_ws[dev].retired) TSNMF_HIP(hipFree(q));
+    g_ws[dev].retired.clear();
     return TSNMF_OK;
 }
 
@@ -201,12 +215,13 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
 }
 
 static const int kMaxSmall = 256;   // p, n bound of the n x n solvers
+static const int kMaxSpaRows = 4096; // p bound of SPA (the rows of a projection)
 static const int kMaxPicks = 64;    // r bound of XRAY and NNLS
 
 int tsnmf_select_spa(const double* M, int32_t p, int32_t n, int32_t ldm, const double* colscale, int32_t r,
                      int32_t* K, double* score, int32_t* info, hipStream_t stream) {
     if (M == nullptr) return -1;
-    if (p < 1 || p > kMaxSmall) return -2;
+    if (p < 1 || p > kMaxSpaRows) return -2;
     if (n < 1 || n > kMaxSmall) return -3;
     if (ldm < p) return -4;
     if (r < 1 || r > n) return -6;
@@ -277,6 +292,11 @@ int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {
         b = b > g ? b : g;
     }
     return workspace_reserve(b);
+}
+
+int tsnmf_workspace_release(void) {
+    if (int st = workspace_release_retired()) return st;
+    return batch_release_retired();
 }
 
 int tsnmf_profile_enable(int on) {

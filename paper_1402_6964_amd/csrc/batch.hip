@@ -74,9 +74,12 @@ __host__ __device__ constexpr int class_of(int64_t n, int64_t ld) {
 __host__ __device__ constexpr int64_t class_block(int c) {
     return c == CLS_S16 ? S16::BR : c == CLS_S32 ? S32::BR : c == CLS_W64 ? W64::BR : W128::BR;
 }
+// Slabs are whole numbers of blocks (512, 320, 1536 and 768 rows).
 __host__ __device__ constexpr int64_t class_slab(int c) {
-    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4096 : c == CLS_W64 ? 7680 : 16128;
+    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4160 : c == CLS_W64 ? 7680 : 16128;
 }
+static_assert(4096 % S16::BR == 0 && 4160 % S32::BR == 0 && 7680 % W64::BR == 0 && 16128 % W128::BR == 0,
+              "default slabs are whole blocks");
 // Nodes per tree group.  For the one-wave classes a group must hold whole
 // items (multiples of kWaves slabs); 24 and 16 are near the fastest pass sizes.
 constexpr int kGroupS16 = 24;
@@ -357,6 +360,9 @@ struct BatchWs {
     int32_t bcap = 0;
     int64_t tcap = 0, dcap = 0;
     int grid = 0;
+    // Buffers replaced by a larger one, kept for graphs captured before the
+    // growth until tsnmf_workspace_release() (or the end of the process).
+    std::vector<void*> retired;
 };
 std::mutex g_bws_mu;
 std::vector<BatchWs> g_bws;
@@ -384,18 +390,14 @@ bool fits(const BatchWs& w, int B, int64_t words, int64_t tickets) {
 int bws_grow(int dev, int B, int64_t words, int64_t tickets) {
     BatchWs& w = g_bws[dev];
     if (fits(w, B, words, tickets)) return TSNMF_OK;
-    const int32_t bc = std::max(w.bcap, B);
-    const int64_t tc = std::max(w.tcap, tickets), dc = std::max(w.dcap, words);
+    // each capacity that grows grows by at least half, so the retired
+    // buffers stay within a small multiple of the live one
+    auto up = [](int64_t have, int64_t need) { return need <= have ? have : std::max(need, have + have / 2); };
+    const int32_t bc = (int32_t)std::min<int64_t>(up(w.bcap, B), TSNMF_MAX_BATCH);
+    const int64_t tc = up(w.tcap, tickets), dc = up(w.dcap, words);
     const size_t bytes = align256(sizeof(BatchHdr)) + align256(sizeof(BatchMat) * (size_t)bc) +
                          align256(sizeof(int64_t) * ((size_t)bc + 1)) + align256(sizeof(int) * (size_t)tc) +
                          sizeof(double) * (size_t)dc;
-    if (w.ptr != nullptr) {
-        TSNMF_HIP(hipDeviceSynchronize());
-        TSNMF_HIP(hipFree(w.ptr));
-        w.ptr = nullptr;
-        w.bcap = 0;
-        w.tcap = w.dcap = 0;
-    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
@@ -403,6 +405,9 @@ int bws_grow(int dev, int B, int64_t words, int64_t tickets) {
         (void)hipGetLastError();
         return TSNMF_ERR_NOMEM;
     }
+    // The old buffer may still be used by enqueued work or by a captured
+    // graph: retire it instead of freeing it.
+    if (w.ptr != nullptr) w.retired.push_back(w.ptr);
     w.ptr = p;
     w.bcap = bc;
     w.tcap = tc;
@@ -426,6 +431,17 @@ int batch_grid(int dev, int* grid) {
 }
 
 }  // namespace
+
+int batch_release_retired() {
+    int dev = 0;
+    TSNMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_bws_mu);
+    if ((int)g_bws.size() <= dev || g_bws[dev].retired.empty()) return TSNMF_OK;
+    TSNMF_HIP(hipDeviceSynchronize());
+    for (void* q : g_bws[dev].retired) TSNMF_HIP(hipFree(q));
+    g_bws[dev].retired.clear();
+    return TSNMF_OK;
+}
 
 int batch_reserve(int32_t max_batch, int64_t max_rows) {
     int dev = 0;

@@ -30,6 +30,9 @@ constexpr int64_t kMaxLeaves = (int64_t)(kTicketBytes / sizeof(int));
 // stream is capturing and the workspace is too small, TSNMF_ERR_NOMEM).
 int workspace_get(size_t bytes, hipStream_t stream, void** out);
 int workspace_reserve(size_t bytes);
+// Free the buffers that growth retired (waits for the device first).
+int workspace_release_retired();
+int batch_release_retired();
 
 // Bytes of workspace one TSQR call of this shape needs (for tsnmf_reserve).
 size_t tsqr_workspace_bytes(int64_t m, int n);

@@ -52,13 +52,16 @@ __device__ double block_sum(double v, double* sv) {
 // ---- SPA (Sec. 2.1) -------------------------------------------------------------
 // Z (p x n, row-major in the workspace) starts as M diag(1/colscale); each pick
 // j* = argmax_j ||Z(:, j)||^2 over unpicked columns, then Z <- Z - u (u^T Z)
-// with u = Z(:, j*) / ||Z(:, j*)||.  Thread j owns column j (n <= 256).
+// with u = Z(:, j*) / ||Z(:, j*)||.  Thread j owns column j (n <= 256); the
+// rows may be as many as the projection's k (p <= kSpaMaxRows), so that SPA
+// also runs on (G^T X) D^{-1} (Sec. 2.3, Sec. 3.3).
+constexpr int kSpaMaxRows = 4096;
 __global__ void __launch_bounds__(kThreads) spa_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                        const double* __restrict__ colscale, int r, int* K,
                                                        double* score, int* info, double* Z) {
     __shared__ double sv[kThreads];
     __shared__ int si[kThreads];
-    __shared__ double u[256];
+    __shared__ double u[kSpaMaxRows];
     const int j = threadIdx.x;
     const bool col = j < n;
     const double sc = (col && colscale != nullptr) ? 1.0 / colscale[j] : 1.0;

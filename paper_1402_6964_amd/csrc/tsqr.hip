@@ -136,10 +136,11 @@ size_t plan_bytes(const Plan& p, int n) {
 
 }  // namespace
 
+// Every default plan (any dtype, layout, leaf precision and row stride) has
+// at most kTargetStreams leaves, and at most m: size the tree for that many.
 size_t tsqr_workspace_bytes(int64_t m, int n) {
-    const Plan p32 = make_plan(m, n, n, TSNMF_F32, nullptr);
-    const Plan p64 = make_plan(m, n, n, TSNMF_F64, nullptr);
-    return std::max(plan_bytes(p32, n), plan_bytes(p64, n));
+    const int64_t nodes = tree_nodes(std::min<int64_t>(m, kTargetStreams));
+    return kTicketBytes + align256(nodes * (size_t)n * n * 8) + align256(nodes * (size_t)n * 8);
 }
 
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,

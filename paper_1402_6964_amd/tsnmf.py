@@ -63,6 +63,7 @@ _select_gp = _sig("tsnmf_select_gp", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, 
 _nnls = _sig("tsnmf_nnls", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp])
 _residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
 _reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
+_workspace_release = _sig("tsnmf_workspace_release", ctypes.c_int, [])
 _profile_enable = _sig("tsnmf_profile_enable", ctypes.c_int, [ctypes.c_int])
 _profile_query = _sig("tsnmf_profile_query", ctypes.c_int,
                       [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
@@ -148,6 +149,10 @@ def tsnmf_residual(M, p, n, ldm, K, r, H, ldh, relerr, stream=None):
 
 def tsnmf_reserve(max_m, max_n, max_k=0):
     return _reserve(max_m, max_n, max_k)
+
+
+def tsnmf_workspace_release():
+    return _workspace_release()
 
 
 def tsnmf_profile_enable(on):

@@ -134,3 +134,38 @@ def test_philox_mutants_are_caught(old, new):
     from oracle import philox
     assert philox_pins_pass(philox)
     assert not philox_pins_pass(mutant("philox", old, new))
+
+
+def xray_pins_pass(sel):
+    """Brute-force XRAY picks (tests.test_oracle_select_nnls) on a few small
+    matrices, and the hand-checked 2 x 3 case."""
+    from tests.test_oracle_select_nnls import _xray_brute
+    ok = True
+    for seed in range(4):
+        rng = np.random.default_rng([302, seed])
+        M = rng.uniform(size=(6, 9))
+        M[:, 3] *= 2.0
+        K, _ = sel.xray(M, 3)
+        ok &= K == _xray_brute(M, 3)
+    for seed in range(6):                # wide and short: later picks differ more
+        rng = np.random.default_rng([303, seed])
+        M = rng.uniform(size=(4, 8))
+        M[:, 1] *= 2.0
+        K, _ = sel.xray(M, 4)
+        ok &= K == _xray_brute(M, 4)
+    M = np.array([[2.0, 0.0, 1.0], [0.0, 1.0, 1.0]])
+    ok &= sel.xray(M, 2)[0] == [0, 1]
+    return bool(ok)
+
+
+@pytest.mark.parametrize("old,new", [
+    ("Res = M - M[:, K] @ H", "Res = M + M[:, K] @ H"),                              # wrong sign
+    ("Res = M - M[:, K] @ H", "Res = M - M[:, K[:1]] @ H[:1]"),                       # only the first pick fitted
+    ("Res = M - M[:, K] @ H", "Res = M"),                                             # residual never updated
+    ("np.linalg.norm(Res.T @ M[:, j])", "np.linalg.norm(M.T @ Res[:, j])"),          # score operands swapped
+    ("np.linalg.norm(Res.T @ M[:, j]) / norms[j]", "np.linalg.norm(Res.T @ M[:, j])"),  # normalisation dropped
+])
+def test_xray_mutants_are_caught(old, new):
+    from oracle import select
+    assert xray_pins_pass(select)
+    assert not xray_pins_pass(mutant("select", old, new))

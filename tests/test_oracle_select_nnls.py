@@ -202,3 +202,65 @@ def test_nnls_entering_index_with_zero_value_terminates(monkeypatch):
     xr, _, _ = on.nnls(A, b)
     assert on.kkt_violation(A, b, xr) <= 1e-10
     assert info in (0, 1)
+
+
+def _xray_brute(M, picks):
+    """Greedy XRAY picks written out independently of the oracle: the NNLS fit
+    of each column on the chosen ones comes from scipy, and for a single chosen
+    column from its closed form h = max(0, a^T b / a^T a)."""
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[1]
+    norms = np.linalg.norm(M, axis=0)
+    K = []
+    Res = M.copy()
+    margins = []
+    for _ in range(picks):
+        sc = {j: np.linalg.norm(Res.T @ M[:, j]) / norms[j] for j in range(n) if j not in K and norms[j] > 0.0}
+        order = sorted(sc, key=lambda j: (-sc[j], j))
+        bj = order[0]
+        if len(order) > 1:
+            margins.append((sc[order[0]] - sc[order[1]]) / sc[order[0]])
+        K.append(bj)
+        A = M[:, K]
+        if len(K) == 1:
+            a = A[:, 0]
+            H = np.maximum(0.0, (a @ M) / (a @ a))[None, :]
+        else:
+            H = np.stack([scipy.optimize.nnls(A, M[:, i])[0] for i in range(n)], axis=1)
+        Res = M - A @ H
+    _xray_brute.margins = margins
+    return K
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_xray_later_picks_brute_force(seed):
+    """Picks 2 and 3 of greedy XRAY (Sec. 2.1): after each pick the residual is
+    M - M(:, K) H with H the nonnegative fit on the chosen columns.  Checked
+    against a brute-force restatement whose fits come from the closed form for
+    one column and from scipy's NNLS for two; the score margins are asserted so
+    the comparison is not decided by rounding."""
+    rng = _rng(302, seed)
+    M = rng.uniform(size=(6, 9))
+    M[:, 3] *= 2.0                     # spread the first scores
+    K, _ = select.xray(M, 3)
+    Kb = _xray_brute(M, 3)
+    assert min(_xray_brute.margins) > 1e-9
+    assert K == Kb
+    M = np.random.default_rng([303, seed]).uniform(size=(4, 8))
+    M[:, 1] *= 2.0
+    Kb = _xray_brute(M, 4)
+    assert min(_xray_brute.margins) > 1e-9
+    assert select.xray(M, 4)[0] == Kb
+
+
+def test_xray_second_pick_by_hand():
+    """A 2 x 3 case small enough to check by hand.  Columns a = (2, 0),
+    b = (0, 1), c = (1, 1).  Pick 1: scores ||M^T x|| / ||x|| are
+    a: ||(4, 0, 2)|| / 2 = sqrt(5), b: ||(0, 1, 1)|| = sqrt(2),
+    c: ||(2, 1, 2)|| / sqrt(2) = 3 / sqrt(2) -> a (sqrt 5 > 2.12).
+    Fit on a: h = max(0, a^T x / 4) = (1, 0, 1/2); Res = M - a h =
+    [(0,0), (0,1), (0,1)].  Pick 2: b: ||Res^T b|| / 1 = ||(0, 1, 1)|| = sqrt 2,
+    c: ||Res^T c|| / sqrt 2 = ||(0, 1, 1)|| / sqrt 2 = 1 -> b."""
+    M = np.array([[2.0, 0.0, 1.0], [0.0, 1.0, 1.0]])
+    K, info = select.xray(M, 2)
+    assert K == [0, 1] and info == 2

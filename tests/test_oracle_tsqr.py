@@ -156,3 +156,19 @@ def test_zero_matrix_and_zero_column():
     R = tsqr.tsqr_r_final(X, leaf_rows=16)
     assert np.all(R[:, 2] == 0.0) or np.abs(R[:, 2]).max() <= 1e-15
     assert np.linalg.norm(R.T @ R - X.T @ X) / np.linalg.norm(X) ** 2 <= 1e-14
+
+
+def test_parallel_oracle_is_bit_identical():
+    """oracle.parallel runs aligned runs of leaves in worker processes and the
+    top of the tree in the parent: the same R as tsqr_r, bit for bit, for
+    several run sizes and a ragged last leaf and run."""
+    from oracle import parallel
+    X = np.random.default_rng(91).uniform(size=(13_457, 7)).astype(np.float32)
+    ref = tsqr.tsqr_r(X, leaf_rows=1000)
+    pool = parallel.OraclePool(2)
+    try:
+        pool.load(X)
+        for run in (None, 1, 2, 4, 16):
+            assert np.array_equal(pool.tsqr_r(1000, run_leaves=run), ref)
+    finally:
+        pool.close()

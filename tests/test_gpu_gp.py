@@ -91,7 +91,7 @@ class Sums:
     over row chunks: Y = G^T X (FP64), Yk = bf16(G)^T bf16(X), |G|^T |X|,
     rho^T |X|, |bf16 G|^T |bf16 X| and the BF16 boundary term."""
 
-    def __init__(self, X, seed, cols=None, row0=0, chunk=1 << 17):
+    def __init__(self, X, seed, cols=None, row0=0, chunk=1 << 17, Xb=None):
         X = np.asarray(X)
         m, n = X.shape
         groups = cols
@@ -106,7 +106,8 @@ class Sums:
             C = np.asarray(X[i:i + chunk], dtype=np.float64)
             rows = np.arange(row0 + i, row0 + i + C.shape[0], dtype=np.uint64)
             G = np.concatenate([oph.gaussian_block(seed, rows, q) for q in groups], axis=1)
-            Gb, Cb = to_bf16(G), to_bf16(C)
+            Gb = to_bf16(G)
+            Cb = to_bf16(C) if Xb is None else np.asarray(Xb[i:i + chunk], dtype=np.float64)
             aC, aCb = np.abs(C), np.abs(Cb)
             self.Y += G.T @ C
             self.Yk += Gb.T @ Cb
@@ -236,6 +237,7 @@ def test_invalid_arguments(lib):
 FULL_GROUPS = [0, 1, 37, 77, 101, 127]
 
 
+@pytest.mark.timeout(400)
 def test_projection_workload_full_size_sampled(lib):
     """The projection workload at full size (20,000,000 x 128, k = 512, BF16 on
     the matrix cores and FP32 on the vector units, the launch bench.py times):
@@ -248,8 +250,9 @@ def test_projection_workload_full_size_sampled(lib):
     seed = 14026964
     Yb, _ = _gp(lib, Xb, 512, seed, mode=lib.GP_MFMA_BF16)
     Ys, _ = _gp(lib, X, 512, seed, mode=lib.GP_SIMD_F32)
+    Xbh = Xb.float().cpu().numpy()                # the BF16 rounding of X, as FP32 values
     del Xb
-    s = Sums(X.cpu().numpy(), seed, cols=FULL_GROUPS, chunk=1 << 19)
+    s = Sums(X.cpu().numpy(), seed, cols=FULL_GROUPS, chunk=1 << 19, Xb=Xbh)
     rows = np.concatenate([np.arange(4 * q, 4 * q + 4) for q in FULL_GROUPS])
     rs = np.abs(Ys[rows] - s.Y) / s.bound_f32()
     rb = np.abs(Yb[rows] - s.Yk) / s.bound_bf16()

@@ -1,0 +1,208 @@
+"""Selected extreme columns K from the GPU path against the oracle's K on the
+same input (the selection must be bit-identical at the planted rank), for the
+workloads the benchmark runs, through the C ABI.
+
+Each test runs the whole GPU path (TSQR or projection, then the selection on
+the GPU) and the whole oracle path (oracle TSQR or projection, reference
+column sums, oracle selection) on the same bytes.  A pick is decided by
+rounding only when its two best scores are within the GPU path's error; the
+relative margin (best - runner-up) / best of every oracle pick is computed and
+required to exceed 20 times the measured relative error of the GPU's R (or Y)
+against the oracle's, so an equal K is the expected outcome and a different K
+is a failure.
+
+Sizes: the flow-cytometry workload at its full 10,000,000 x 25; the
+heat-transfer workload's generator at 4,000,000 x 64 column-major (its full
+50,000,000 rows would take the single-threaded oracle several minutes); the
+projection workload's generator at 200,000 x 128 with k = 512 (the full
+20,000,000 rows are checked entry by entry in test_gpu_gp.py); sixteen
+matrices of the 512-matrix batch, four of every width.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gauss_proj as ogp
+from oracle import philox as oph
+from oracle import select as osel
+from oracle import tsqr as otsqr
+from paper_1402_6964_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def spa_margins(M, K, colscale):
+    """Relative margin of every pick of SPA (oracle order K) on M diag(1/d)."""
+    Z = np.asarray(M, dtype=np.float64) / np.asarray(colscale)[None, :]
+    out, chosen = [], []
+    for j in K:
+        s = np.sum(Z * Z, axis=0)
+        s[chosen] = -np.inf
+        top = np.sort(s)[::-1]
+        assert int(np.argmax(s)) == j
+        out.append((top[0] - top[1]) / top[0] if len(top) > 1 else 1.0)
+        chosen.append(j)
+        u = Z[:, j] / np.sqrt(s[j])
+        Z = Z - np.outer(u, u @ Z)
+    return np.asarray(out)
+
+
+def gp_row_margins(Y, colscale):
+    """Per row of Y diag(1/d): relative gaps of the min and of the max to the
+    runners-up, against the row's largest magnitude."""
+    Yn = np.asarray(Y, dtype=np.float64) / np.asarray(colscale)[None, :]
+    srt = np.sort(Yn, axis=1)
+    scale = np.abs(Yn).max(axis=1)
+    return np.minimum(srt[:, 1] - srt[:, 0], srt[:, -1] - srt[:, -2]) / scale
+
+
+def _gpu_spa(lib, R, cs, r):
+    K, _, info = lib.select_spa(R, r, colscale=cs)
+    torch.cuda.synchronize()
+    assert int(info.item()) == r
+    return K.cpu().tolist()
+
+
+def _oracle_k(Xh, r, leaf_rows=1000):
+    Ro = otsqr.tsqr_r_final(Xh, leaf_rows=leaf_rows)
+    d = otsqr.reference_sums(Xh)[0]
+    Ko, _, _ = osel.spa(Ro, r, colscale=d)
+    return Ko, Ro, d
+
+
+def _r_error(R, Ro):
+    Rg = R.cpu().numpy()
+    return float(np.abs(Rg - Ro).max() / np.abs(Ro).max())
+
+
+@pytest.mark.timeout(300)
+def test_flow_cytometry_full_size_k(lib):
+    """10,000,000 x 25 FP32 row-major, r = 16: FP32 leaves + FP64 tree, then
+    SPA on R D^{-1}, all on the GPU; the oracle's TSQR (1,000-row leaves,
+    binary tree) and SPA on the same bytes."""
+    d = synth.flow_cytometry(device="cuda")
+    X = d["X"]
+    R, cs = lib.tsqr_r(X)
+    K = _gpu_spa(lib, R, cs, d["r"])
+    Xh = X.cpu().numpy()
+    del X
+    torch.cuda.empty_cache()
+    Ko, Ro, do = _oracle_k(Xh, d["r"])
+    mg = spa_margins(Ro, Ko, do)
+    e = _r_error(R, Ro)
+    print(f"K = {K}; smallest margin {mg.min():.2e}; R error {e:.2e}")
+    assert mg.min() > 20 * e
+    assert K == Ko
+    assert sorted(Ko) == d["K"]
+
+
+@pytest.mark.timeout(300)
+def test_heat_transfer_k(lib):
+    """The heat-transfer generator at 4,000,000 x 64, column-major (ld = m),
+    r = 20."""
+    d = synth.heat_transfer(m=4_000_000, device="cuda")
+    X = d["X"]
+    R, cs = lib.tsqr_r(X)
+    K = _gpu_spa(lib, R, cs, d["r"])
+    Xh = np.ascontiguousarray(X.cpu().numpy())
+    del X, d["X"]
+    torch.cuda.empty_cache()
+    Ko, Ro, do = _oracle_k(Xh, d["r"])
+    mg = spa_margins(Ro, Ko, do)
+    e = _r_error(R, Ro)
+    print(f"K = {K}; smallest margin {mg.min():.2e}; R error {e:.2e}")
+    assert mg.min() > 20 * e
+    assert K == Ko
+    assert sorted(Ko) == d["K"]
+
+
+def _to_bf16(a):
+    x = np.asarray(a, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", ["simd", "mfma"])
+def test_projection_k(lib, mode):
+    """The projection generator at 200,000 x 128, k = 512, r = 32: GP selection
+    (Sec. 2.3) and SPA on (G^T X) D^{-1} (Sec. 3.3), from the GPU's Y and
+    column sums, against the oracle's K on the oracle's Y (on the BF16-rounded
+    inputs for the matrix-core run).  Rows of Y whose argmin or argmax is
+    within the projection's error of a runner-up are counted; the selection is
+    compared where such rows cannot change it."""
+    m, k, seed = 200_000, 512, 14026964
+    d = synth.projection(m=m, device="cuda")
+    X = d["X"]
+    r = d["r"]
+    if mode == "simd":
+        Yg, csg = lib.gauss_proj(X, k, seed, mode=lib.GP_SIMD_F32, with_colsum=True)
+        Xh = X.cpu().numpy().astype(np.float64)
+        Yo = ogp.gauss_proj(Xh, k, seed)
+    else:
+        Xb = X.to(torch.bfloat16)
+        Yg, csg = lib.gauss_proj(Xb, k, seed, mode=lib.GP_MFMA_BF16, with_colsum=True)
+        Xh = Xb.float().cpu().numpy().astype(np.float64)
+        Yo = _to_bf16(oph.gaussian_matrix(seed, 0, m, k)).T @ Xh
+    torch.cuda.synchronize()
+    do = otsqr.reference_sums(Xh)[0]
+    assert np.max(np.abs(csg.cpu().numpy() - do) / do) <= 1e-12
+    Yh = Yg.cpu().numpy().astype(np.float64)
+    e = float(np.abs(Yh - Yo).max() / np.abs(Yo).max())       # the GPU path's error
+    # GP selection: a row is ambiguous when its argmin or argmax gap is within
+    # twice that row's own error (both relative to the row's largest entry)
+    Yn, Yon = Yh / do[None, :], Yo / do[None, :]
+    row_err = np.abs(Yn - Yon).max(axis=1) / np.abs(Yon).max(axis=1)
+    amb = gp_row_margins(Yo, do) <= 2 * row_err
+    Kg, cg, _ = lib.select_gp(Yg, r, colscale=csg)
+    Kgo, cgo, _ = osel.gp_select(Yo, r, colscale=do)
+    print(f"{mode}: Y error {e:.2e}; GP K = {Kg.cpu().tolist()}; ambiguous rows {int(amb.sum())}")
+    cg = cg.cpu().numpy()
+    na = int(amb.sum())
+    # each ambiguous row can move two counts by one
+    assert np.abs(cg - np.asarray(cgo)).sum() <= 2 * na
+    if na == 0:
+        assert Kg.cpu().tolist() == Kgo and np.array_equal(cg, cgo)
+    else:
+        srt = np.sort(np.asarray(cgo))[::-1]
+        assert srt[r - 1] - srt[r] > 2 * na          # the set is decided regardless
+        assert sorted(Kg.cpu().tolist()) == sorted(Kgo)
+    # SPA on the projection, normalised by the column sums
+    Kso, _, _ = osel.spa(Yo, r, colscale=do)
+    mg = spa_margins(Yo, Kso, do)
+    Ks = _gpu_spa(lib, Yg.double(), csg, r)
+    print(f"{mode}: SPA K = {Ks}; smallest margin {mg.min():.2e}")
+    assert mg.min() > 20 * e
+    assert Ks == Kso
+
+
+@pytest.mark.timeout(600)
+def test_batched_sample_k(lib):
+    """The 512-matrix batched workload in one call: sixteen matrices (four per
+    width, the 0th, 10th, 20th and 30th percentiles of m within the width),
+    each with SPA at r = n / 4 on the batched R against the oracle's K."""
+    shapes = synth.batch_shapes()
+    mats = [synth.batch_matrix(q, m, n, device="cuda") for q, (m, n) in enumerate(shapes)]
+    b = lib.Batch([t["X"] for t in mats])
+    b.run()
+    torch.cuda.synchronize()
+    res = b.results()
+    picks = []
+    for n in (16, 32, 64, 128):
+        idx = sorted((i for i, s in enumerate(shapes) if s[1] == n), key=lambda i: shapes[i][0])
+        picks += [idx[int(p * (len(idx) - 1))] for p in (0.0, 0.1, 0.2, 0.3)]
+    for q in picks:
+        t = mats[q]
+        r = t["r"]
+        R, cs = res[q]
+        K = _gpu_spa(lib, R, cs, r)
+        Xh = t["X"].cpu().numpy()
+        Ko, Ro, do = _oracle_k(Xh, r)
+        mg = spa_margins(Ro, Ko, do)
+        e = _r_error(R, Ro)
+        print(f"matrix {q} {shapes[q]}: K {K}; smallest margin {mg.min():.2e}; R error {e:.2e}", flush=True)
+        assert mg.min() > 20 * e
+        assert K == Ko
+        assert sorted(Ko) == t["K"]

@@ -353,3 +353,83 @@ def test_profiling_modes(lib):
         st0, ms0, c0 = lib.tsnmf_profile_query(0)
         st1, ms1, c1 = lib.tsnmf_profile_query(1)
         assert st0 == 0 and st1 == 0 and c0 == 3 and c1 == tree_calls and ms0 > 0.0
+
+
+def _layout_view(store_rows, m, n, layout, dt, tag):
+    """X (m x n) as row-major contiguous, column-major (ld = m) or row-major
+    with a padded row stride (ld = n + 5, offset 2)."""
+    if layout == "row":
+        base = synth.random_matrix(m, n, dtype=dt, seed_tag=tag, dist="uniform").cuda()
+        return base, base
+    if layout == "col":
+        base = synth.random_matrix(n, m, dtype=dt, seed_tag=tag, dist="uniform").cuda()
+        return base.t(), base
+    base = synth.random_matrix(m, n + 5, dtype=dt, seed_tag=tag, dist="uniform").cuda()
+    return base[:, 2:2 + n], base
+
+
+@pytest.mark.parametrize("layout", ["row", "col", "padded"])
+@pytest.mark.parametrize("n", [20, 96])
+@pytest.mark.parametrize("path", ["f64", "f32_leaf_f64"])
+def test_fp64_paths_every_layout(lib, path, n, layout):
+    """The FP64 leaf kernels (FP64 input, and FP32 input with TSNMF_LEAF_F64)
+    on every layout: row-major contiguous, column-major and a padded row
+    stride, small and wide widths, at the FP64 tolerances."""
+    dt = torch.float64 if path == "f64" else torch.float32
+    X, _ = _layout_view(None, 60_007, n, layout, dt, 400 + n)
+    Rg, csg = _run(lib, X, leaf_f64=(path != "f64"))
+    _check_against_oracle(Rg, csg, X.cpu().numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
+
+
+def test_graph_capture_single_calls_survive_growth(lib):
+    """tsnmf_tsqr_r and tsnmf_gauss_proj captured into one graph after
+    tsnmf_reserve; every replay (with eager work and synchronisation between
+    replays, and new data in the same input buffer) matches an eager call.  A
+    larger uncaptured call in between grows the workspace: the captured graph
+    still names the old buffer, which the library keeps (not frees), so later
+    replays stay correct."""
+    m, n, k = 300_001, 25, 64
+    lib.reserve(m, n, k)
+    X = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=410).cuda()
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    cs = torch.empty(n, dtype=torch.float64, device="cuda")
+    Y = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+
+    def calls(stream):
+        assert lib.tsnmf_tsqr_r(X, m, n, n, lib.F32, R, cs, stream) == 0
+        assert lib.tsnmf_gauss_proj(X, m, n, n, lib.F32 | lib.GP_SIMD_F32, k, 5, 0, Y, None, stream) == 0
+
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        calls(s.cuda_stream)
+    torch.cuda.synchronize()
+
+    def eager():
+        Re = torch.empty_like(R)
+        ce = torch.empty_like(cs)
+        Ye = torch.empty_like(Y)
+        st = torch.cuda.current_stream().cuda_stream
+        assert lib.tsnmf_tsqr_r(X, m, n, n, lib.F32, Re, ce, st) == 0
+        assert lib.tsnmf_gauss_proj(X, m, n, n, lib.F32 | lib.GP_SIMD_F32, k, 5, 0, Ye, None, st) == 0
+        torch.cuda.synchronize()
+        return Re.cpu(), ce.cpu(), Ye.cpu()
+
+    for rep in range(4):
+        if rep == 2:
+            # grow the workspace from outside the graph
+            big = synth.random_matrix(2_000_000, 128, dtype=torch.float32, seed_tag=411).cuda()
+            Rb, _ = lib.tsqr_r(big)
+            torch.cuda.synchronize()
+            del big
+        X.mul_(1.5)                       # new data in the captured input buffer
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        Rg, cg, Yg = R.cpu(), cs.cpu(), Y.cpu()
+        Re, ce, Ye = eager()
+        assert torch.equal(Rg, Re) and torch.equal(cg, ce) and torch.equal(Yg, Ye), f"replay {rep}"
+    _check_against_oracle(R.t().cpu().numpy(), cs.cpu().numpy(), X.cpu().numpy(), 1e-6, 2e-5, 1e-6, norm_tol=1e-5)
+    del g
+    assert lib.tsnmf_workspace_release() == 0

@@ -67,7 +67,8 @@ extern "C" {
 #define TSNMF_ERR_CAPTURE      3  /* workspace too small while stream capturing   */
 #define TSNMF_ERR_UNSUPPORTED  4  /* shape outside the supported range            */
 
-#define TSNMF_MAX_N 128           /* largest column count of the TSQR / GP paths */
+#define TSNMF_MAX_N 256           /* largest column count of the TSQR / GP paths */
+#define TSNMF_MAX_BATCH_N 128     /* largest column count of the batched TSQR    */
 
 /* ---- thin QR, R factor only ------------------------------------------------- */
 
@@ -95,6 +96,8 @@ extern "C" {
  * factorisations of stacked factors (groups of several factors per node), in
  * a second launch that climbs all levels by ticket.  The result is
  * deterministic for a given (m, n, flags, configuration).
+ * The launch geometry is the library default, or the entry of the loaded
+ * autotune table (tsnmf_tune_load) that matches the call.
  * Errors: -1 X NULL, -2 m < 1, -3 n < 1, -4 ld too small, -5 flags, -6 R NULL,
  * TSNMF_ERR_UNSUPPORTED for n > TSNMF_MAX_N.
  */
@@ -116,7 +119,8 @@ typedef struct tsnmf_tsqr_config {
 } tsnmf_tsqr_config;
 
 /* As tsnmf_tsqr_r with an explicit configuration (`cfg` is a host pointer or
-   NULL).  Every configuration gives the same R up to rounding. */
+   NULL: the library default, without the autotune table).  Every
+   configuration gives the same R up to rounding. */
 int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
                     double* R, double* colsum, const tsnmf_tsqr_config* cfg,
                     hipStream_t stream);
@@ -134,7 +138,8 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
  *   batch   number of matrices, 1..TSNMF_MAX_BATCH (host value).
  *   X       device array of `batch` device pointers, FP32 row-major matrices.
  *   m, n, ld  device arrays of `batch` int64: rows, columns, leading
- *           dimension of each matrix (1 <= n <= TSNMF_MAX_N, m >= 1, ld >= n).
+ *           dimension of each matrix (1 <= n <= TSNMF_MAX_BATCH_N, m >= 1,
+ *           ld >= n).
  *   flags   TSNMF_F32 (row-major); FP32 row blocks, FP64 R and trees.
  *   R       device array of `batch` device pointers to n x n FP64
  *           column-major outputs (diag(R) >= 0, R^T R = X^T X).
@@ -142,7 +147,7 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
  *           entry may be NULL), or NULL for no column sums.
  * The arrays are read on the device when the work runs, so a captured graph
  * may be replayed with new pointers and shapes in the same arrays.  A matrix
- * whose entry is invalid (NULL X or R, n outside 1..TSNMF_MAX_N, m < 1,
+ * whose entry is invalid (NULL X or R, n outside 1..TSNMF_MAX_BATCH_N, m < 1,
  * ld < n, or n > 64 with ld >= 2^23: those matrices are read in 64-row
  * chunks through 32-bit buffer offsets) is skipped; its R and column sums
  * are set to NaN when R is not NULL and n is in range.  Matrices are scheduled largest-first by m n^2.
@@ -270,6 +275,16 @@ int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int
    k <= max_k, need no allocation (required before graph capture).  Host
    call, synchronous. */
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k);
+
+/* Load the autotune table (host path of a text file written by the library's
+   autotuner; NULL clears the table).  Each line
+       tsqr <f32|f64> <row|col> <leaf f32|f64> <ld==n 1|0> <n> <floor(log2 m)> <leaf_rows> <tree_arity>
+   gives the launch geometry (as tsnmf_tsqr_config) that tsnmf_tsqr_r applies
+   to calls with that input dtype, layout, row-block precision, contiguity,
+   width and row-count bucket; '#' starts a comment.  Calls without an entry
+   use the library default.  Returns 0, or -1 if the file cannot be read or a
+   line is malformed (the previous table is then kept).  Host call. */
+int tsnmf_tune_load(const char* path);
 
 /* Free the workspace buffers that growth has retired on the current device
    (single-call and batched), after waiting for the device.  Graphs captured

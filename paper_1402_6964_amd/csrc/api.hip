@@ -173,7 +173,9 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
 
 int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, double* R,
                  double* colsum, hipStream_t stream) {
-    return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, nullptr, stream);
+    tsnmf_tsqr_config tuned{};
+    const bool have = n >= 1 && n <= TSNMF_MAX_N && m >= 1 && tune_lookup(flags, m, (int)n, ld, &tuned);
+    return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, have ? &tuned : nullptr, stream);
 }
 
 int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
@@ -342,6 +344,6 @@ const char* tsnmf_status_string(int status) {
 
 int tsnmf_last_hip_error(void) { return g_last_hip; }
 
-int tsnmf_version(void) { return 100; }
+int tsnmf_version(void) { return 200; }
 
 }  // extern "C"

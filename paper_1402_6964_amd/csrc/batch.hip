@@ -39,6 +39,7 @@ constexpr int kWaves = 8;                                   // waves per workgro
 // per-element loads: 71.4 -> 69.3 ms on the 512-matrix workload; the
 // 64-column class keeps per-element loads, which measured faster there).
 constexpr int64_t kMaxBatchLd = (int64_t)1 << 23;
+constexpr int64_t kMaxBatchN = 128;      // widest matrix of the batched call
 constexpr int kRplS16 = 8;        // one-wave classes: 512- and 320-row blocks
 constexpr int kRplS32 = 5;
 constexpr int kRplW64 = 24;       // 8 columns per wave
@@ -169,10 +170,10 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
     // 1. validity and cost; invalid matrices get NaN outputs when their R fits
     for (int i = t; i < B; i += kPlanThreads) {
         const int64_t mi = m[i], ni = n[i], li = ld[i];
-        const bool ok = X[i] != nullptr && R[i] != nullptr && ni >= 1 && ni <= TSNMF_MAX_N && mi >= 1 && li >= ni &&
+        const bool ok = X[i] != nullptr && R[i] != nullptr && ni >= 1 && ni <= kMaxBatchN && mi >= 1 && li >= ni &&
                         (ni <= 64 || li < kMaxBatchLd);
         cost[i] = ok ? (float)mi * (float)(ni * ni) : -1.0f;
-        if (!ok && R[i] != nullptr && ni >= 1 && ni <= TSNMF_MAX_N) {
+        if (!ok && R[i] != nullptr && ni >= 1 && ni <= kMaxBatchN) {
             const double nan = __builtin_nan("");
             for (int64_t q = 0; q < ni * ni; ++q) R[i][q] = nan;
             double* cs = colsum != nullptr ? colsum[i] : nullptr;
@@ -369,10 +370,10 @@ std::vector<BatchWs> g_bws;
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Smallest tree storage that always fits B matrices of width <= TSNMF_MAX_N
+// Smallest tree storage that always fits B matrices of width <= kMaxBatchN
 // (one node per matrix after enough slab doubling).
 void minimum_need(int B, int64_t* words, int64_t* tickets) {
-    const int64_t nm = TSNMF_MAX_N;
+    const int64_t nm = kMaxBatchN;
     *words = (int64_t)B * (nm * nm + nm);
     *tickets = (int64_t)B * 4;
 }
@@ -448,10 +449,10 @@ int batch_reserve(int32_t max_batch, int64_t max_rows) {
     TSNMF_HIP(hipGetDevice(&dev));
     int64_t w0 = 0, k0 = 0;
     minimum_need(max_batch, &w0, &k0);
-    // all rows in matrices of width TSNMF_MAX_N at the default slabs bound the
+    // all rows in matrices of width kMaxBatchN at the default slabs bound the
     // tree storage; the narrowest class's slabs bound the tickets
-    const Sizes s = matrix_sizes(max_rows, TSNMF_MAX_N, CLS_W128, 0);
-    const int64_t words = w0 + s.words + (int64_t)max_batch * (TSNMF_MAX_N * TSNMF_MAX_N + TSNMF_MAX_N);
+    const Sizes s = matrix_sizes(max_rows, kMaxBatchN, CLS_W128, 0);
+    const int64_t words = w0 + s.words + (int64_t)max_batch * (kMaxBatchN * kMaxBatchN + kMaxBatchN);
     const int64_t tickets = k0 + 2 * (max_rows / class_slab(CLS_S16) + 1) + 2 * (int64_t)max_batch;
     std::lock_guard<std::mutex> lk(g_bws_mu);
     if ((int)g_bws.size() <= dev) g_bws.resize(dev + 1);
@@ -475,7 +476,7 @@ int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const i
         TSNMF_HIP(hipStreamSynchronize(stream));
         int64_t w = 0, k = 0;
         for (int i = 0; i < B; ++i) {
-            if (hn[i] < 1 || hn[i] > TSNMF_MAX_N || hm[i] < 1 || hl[i] < hn[i] || (hn[i] > 64 && hl[i] >= kMaxBatchLd))
+            if (hn[i] < 1 || hn[i] > kMaxBatchN || hm[i] < 1 || hl[i] < hn[i] || (hn[i] > 64 && hl[i] >= kMaxBatchLd))
                 continue;
             const Sizes s = matrix_sizes(hm[i], hn[i], class_of(hn[i], hl[i]), 0);
             w += s.words;

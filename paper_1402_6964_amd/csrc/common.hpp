@@ -50,6 +50,9 @@ int profile_event(hipStream_t s, hipEvent_t* ev);
 void profile_split(hipStream_t s);
 bool profile_take_split(hipEvent_t* end0, hipEvent_t* begin1);
 
+// Entry of the loaded autotune table for this call, if any.
+bool tune_lookup(uint32_t flags, int64_t m, int n, int64_t ld, tsnmf_tsqr_config* out);
+
 // Implementations behind the C entry points (arguments already validated).
 int select_spa_impl(const double* M, int p, int n, int ldm, const double* colscale, int r, int* K, double* score,
                     int* info, hipStream_t stream);
@@ -66,6 +69,7 @@ int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const i
                       double* const* R, double* const* colsum, hipStream_t stream);
 int batch_reserve(int32_t max_batch, int64_t max_rows);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
-                double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream);
+                double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream, void* fixed_ws = nullptr,
+                size_t fixed_bytes = 0);
 
 }  // namespace tsnmf

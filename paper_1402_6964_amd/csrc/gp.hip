@@ -103,7 +103,10 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
     __shared__ double cs_sh[4][128];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
-    const int n = a.n, k = a.k;
+    // grid.z: block of 128 columns (columns cb .. cb + n - 1 of X and Y)
+    const int cb = (int)blockIdx.z * 128;
+    const int n = min(128, a.n - cb), k = a.k;
+    const int64_t ldp = a.n;                         // row length of the partial Y
     const int NT = (n + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
@@ -123,7 +126,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
             // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply
             // per chunk, then one add per row
             const int64_t ib = i0 + rgrp * 8;
-            int64_t idx = ib * a.ld + col_ld;
+            int64_t idx = ib * a.ld + cb + col_ld;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const float v = ib + t < r1 ? load_f32(a.X, idx, bf16_in) : 0.0f;
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
         }
     }
     // partial Y: tile (s, nt), element (row rho = 4 (L / 16) + e, column L % 16)
-    float* P = a.part + (int64_t)blockIdx.x * k * n;
+    float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -162,13 +165,14 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int l = 4 * ((lbase >> 2) + 4 * (L >> 4) + e) + s;
-                if (nt < NT && c < n && l < k) P[(int64_t)l * n + c] = acc[s][nt][e];
+                if (nt < NT && c < n && l < k) P[(int64_t)l * ldp + c] = acc[s][nt][e];
             }
         }
     if (a.part_cs != nullptr && blockIdx.y == 0) {
         cs_sh[rgrp][col_ld] = csum;
         __syncthreads();
-        if (tid < n) a.part_cs[(int64_t)blockIdx.x * n + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+        if (tid < n)
+            a.part_cs[(int64_t)blockIdx.x * ldp + cb + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
     }
 }
 
@@ -188,7 +192,9 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
     __shared__ double cs_sh[4][128];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
-    const int n = a.n, k = a.k;
+    const int cb = (int)blockIdx.z * 128;            // block of 128 columns
+    const int n = min(128, a.n - cb), k = a.k;
+    const int64_t ldp = a.n;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
     const int lbase = blockIdx.y * 512;
@@ -209,7 +215,7 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
                 const int rr = tid >> 7, c = tid & 127;
                 const int64_t i = i0 + rr;
                 float v = 0.0f;
-                if (c < n && i < r1) v = load_f32(a.X, i * a.ld + c, false);
+                if (c < n && i < r1) v = load_f32(a.X, i * a.ld + cb + c, false);
                 csum += (double)__builtin_fabsf(v);
                 xsm[buf][rr][c] = v;
             }
@@ -235,20 +241,21 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
                 for (int c = 0; c < 16; ++c) acc[e][c] = __builtin_fmaf(gv[e], xv[c], acc[e][c]);
         }
     }
-    float* P = a.part + (int64_t)blockIdx.x * k * n;
+    float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int l = lbase + (e < 4 ? 4 * L + e : 256 + 4 * L + (e - 4));
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const int cc = 16 * wv + c;
-            if (cc < n && l < k) P[(int64_t)l * n + cc] = acc[e][c];
+            if (cc < n && l < k) P[(int64_t)l * ldp + cc] = acc[e][c];
         }
     }
     if (a.part_cs != nullptr && blockIdx.y == 0) {
         if (tid < kSimdRows * 128) cs_sh[tid >> 7][tid & 127] = csum;
         __syncthreads();
-        if (tid < n) a.part_cs[(int64_t)blockIdx.x * n + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+        if (tid < n)
+            a.part_cs[(int64_t)blockIdx.x * ldp + cb + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
     }
 }
 
@@ -306,7 +313,8 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
     a.rows_per_wg = rpw;
     a.part = (float*)((char*)ws + kTicketBytes);
     a.part_cs = colsum != nullptr ? (double*)((char*)ws + kTicketBytes + (size_t)parts * k * n * 4) : nullptr;
-    const dim3 grid((unsigned)parts, (unsigned)((k + 511) / 512));
+    // grid: row ranges x 512-wide l-ranges x 128-wide column blocks
+    const dim3 grid((unsigned)parts, (unsigned)((k + 511) / 512), (unsigned)((n + 127) / 128));
     const bool prof = profiling_on();
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
     if (prof) {

@@ -1,6 +1,8 @@
 // Host planning of one TSQR call: leaf launch over row slabs, FP64 tree
 // levels over the stacked slab factors, and the finalisation of R.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "tsqr_wide.hpp"
@@ -26,6 +28,13 @@ hipError_t launch_wide_f64_rowbuf(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_rowbuf(const WideArgs& a, hipStream_t s);
 int rows_per_lane_f32(int n, bool staged);
 int rows_per_lane_f64(int n, bool staged);
+hipError_t launch_xl_f32_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_xl_f32_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_xl_f64_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_xl_f64_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_xl_f32w_row(const WideArgs& a, hipStream_t s);
+hipError_t launch_xl_f32w_col(const WideArgs& a, hipStream_t s);
+size_t xl_rslot_bytes();
 
 namespace {
 
@@ -51,6 +60,14 @@ hipError_t launch_leaf(Path p, int load, int n, const StreamArgs& a, hipStream_t
 
 hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
     const bool col = load == LOAD_COL, buf = load == LOAD_ROW_BUF;
+    if (a.n > 128) {
+        switch (p) {
+            case Path::F32: return col ? launch_xl_f32_col(a, s) : launch_xl_f32_row(a, s);
+            case Path::F64: return col ? launch_xl_f64_col(a, s) : launch_xl_f64_row(a, s);
+            case Path::F32W: return col ? launch_xl_f32w_col(a, s) : launch_xl_f32w_row(a, s);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (p) {
         case Path::F32:
             return col ? launch_wide_f32_col(a, s) : buf ? launch_wide_f32_rowbuf(a, s) : launch_wide_f32_row(a, s);
@@ -72,7 +89,8 @@ struct Plan {
     int64_t streams;
 };
 
-Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_config* cfg) {
+Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_config* cfg,
+               int64_t max_leaves = kMaxLeaves) {
     Plan p{};
     const uint32_t dt = flags & TSNMF_DTYPE_MASK;
     const bool col = (flags & TSNMF_COL_MAJOR) != 0;
@@ -93,12 +111,14 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     const int64_t esize = dt == TSNMF_F64 ? 8 : 4;
     const bool f32 = p.path == Path::F32;
     const int rpl_buf = f32 ? 12 : 5;
-    if (p.wide && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
+    if (p.wide && n <= 128 && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
-    const int rpl = p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
-                              : f32 ? (f32_8x8 ? 22 : (n <= 64 && !col ? 12 : 11)) : 4)
-                           : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
-                                                  : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
+    // above 128 columns: 8 waves x 32 columns, FP32 4 rows per lane, FP64 2
+    const int rpl = n > 128 ? (f32 ? 4 : 2)
+                    : p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
+                                : f32 ? (f32_8x8 ? 22 : (n <= 64 && !col ? 12 : 11)) : 4)
+                             : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
+                                                    : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));
     p.block_rows = 64LL * rpl;
     if (cfg != nullptr && cfg->leaf_rows > 0) {
         p.slab = cfg->leaf_rows;
@@ -107,8 +127,10 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
         const int64_t streams = std::max<int64_t>(1, std::min<int64_t>(blocks, kTargetStreams / p.waves));
         p.slab = ((blocks + streams - 1) / streams) * p.block_rows;
     }
-    // the ticket area bounds the number of leaves
-    p.slab = std::max<int64_t>(p.slab, (m + kMaxLeaves - 1) / kMaxLeaves);
+    // the ticket area (or a fixed scratch buffer) bounds the number of leaves
+    if (max_leaves > kMaxLeaves) max_leaves = kMaxLeaves;
+    if (max_leaves < 1) max_leaves = 1;
+    p.slab = std::max<int64_t>(p.slab, (m + max_leaves - 1) / max_leaves);
     p.streams = (m + p.slab - 1) / p.slab;
     // the FP32 staged loads address a slab through a 32-bit byte range
     if (p.load == LOAD_ROW_STAGED && p.path == Path::F32 && p.slab * n * 4 > kMaxBufSlabBytes) p.load = LOAD_ROW;
@@ -129,25 +151,45 @@ int64_t tree_nodes(int64_t leaves) {
     return total + 2;
 }
 
-size_t plan_bytes(const Plan& p, int n) {
-    const int64_t nodes = tree_nodes(p.streams);
-    return kTicketBytes + align256(nodes * (size_t)n * n * 8) + align256(nodes * (size_t)n * 8);
+// Tickets | tree nodes | node column sums | (n > 128) one global R slot per leaf.
+size_t tree_bytes(int64_t leaves, int n) {
+    const int64_t nodes = tree_nodes(leaves);
+    return kTicketBytes + align256(nodes * (size_t)n * n * 8) + align256(nodes * (size_t)n * 8) +
+           (n > 128 ? align256((size_t)leaves * xl_rslot_bytes()) : 0);
 }
+
+size_t plan_bytes(const Plan& p, int n) { return tree_bytes(p.streams, n); }
+
+// Most leaves whose tree (and R slots) fit `bytes` of workspace.
+int64_t fixed_leaves(int n, size_t bytes) {
+    int64_t lo = 1, hi = kMaxLeaves;                  // tree_bytes grows with the leaves
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (tree_bytes(mid, n) <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 
 }  // namespace
 
 // Every default plan (any dtype, layout, leaf precision and row stride) has
 // at most kTargetStreams leaves, and at most m: size the tree for that many.
-size_t tsqr_workspace_bytes(int64_t m, int n) {
-    const int64_t nodes = tree_nodes(std::min<int64_t>(m, kTargetStreams));
-    return kTicketBytes + align256(nodes * (size_t)n * n * 8) + align256(nodes * (size_t)n * 8);
-}
+size_t tsqr_workspace_bytes(int64_t m, int n) { return tree_bytes(std::min<int64_t>(m, kTargetStreams), n); }
 
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
-                double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream) {
-    const Plan p = make_plan(m, n, ld, flags, cfg);
+                double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream, void* fixed_ws,
+                size_t fixed_bytes) {
+    // With a fixed buffer the slabs are lengthened until the tree fits it.
+    const Plan p = make_plan(m, n, ld, flags, cfg, fixed_ws != nullptr ? fixed_leaves(n, fixed_bytes) : kMaxLeaves);
     void* ws = nullptr;
-    if (int st = workspace_get(plan_bytes(p, n), stream, &ws)) return st;
+    if (fixed_ws != nullptr) {
+        if (plan_bytes(p, n) > fixed_bytes) return TSNMF_ERR_UNSUPPORTED;
+        ws = fixed_ws;
+    } else if (int st = workspace_get(plan_bytes(p, n), stream, &ws)) {
+        return st;
+    }
     const int64_t nodes = tree_nodes(p.streams);
     char* base = (char*)ws;
     TreeArgs tree{};
@@ -158,6 +200,9 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
     tree.R = R;
     tree.colsum = colsum;
     tree.group = cfg != nullptr && cfg->tree_arity > 0 ? cfg->tree_arity : 0;
+    tree.rglob = n > 128 ? (double*)(base + kTicketBytes + align256(nodes * (size_t)n * n * 8) +
+                                     align256(nodes * (size_t)n * 8))
+                         : nullptr;
     StreamArgs a{};
     a.X = X;
     a.m = m;

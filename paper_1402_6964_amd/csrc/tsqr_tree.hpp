@@ -22,6 +22,8 @@ struct TreeArgs {
     double* colsum;      // final column sums or nullptr
     int32_t group;       // nodes per tree group (n <= 32 trees); 0 = the default
     int32_t pad_;
+    double* rglob;       // running R of every workgroup of the wide kernels whose R
+                         // does not fit in LDS (n > 128), one slot per workgroup
 };
 
 __device__ __forceinline__ void grid_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }

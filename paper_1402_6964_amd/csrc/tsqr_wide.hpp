@@ -1,4 +1,4 @@
-// Streaming Householder TSQR for 33..128 columns: W waves per slab, each wave
+// Streaming Householder TSQR for 33..256 columns: W waves per slab, each wave
 // owning every W-th column (wave w holds columns w, w + W, ...; NW <= 32 per
 // wave) of the same 64 * RPL rows of a block.
 //
@@ -35,8 +35,11 @@ struct WideArgs {
 
 // R is kept in FP64 (like the small kernel), compactly: wave w stores, for
 // each row j, only its columns k >= j, i.e. local columns c0(j)..NW-1 with
-// c0(j) = ceil((j - w) / W) (0 for j <= w), row after row.
-template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
+// c0(j) = ceil((j - w) / W) (0 for j <= w), row after row.  Up to 128 columns
+// it lives in LDS; above (RG) it does not fit (n = 256 needs 257 KB in FP64)
+// and lives in a global slot of the workgroup, each wave touching only its
+// own part (so its own program order orders the accesses).
+template <typename T, typename TI, int NW, int W, int RPL, bool RG = false> struct Wide {
     static constexpr int P = ilog2(NW);
     static_assert((1 << P) == NW && NW <= 32, "NW must be a power of two <= 32");
     static constexpr int BR = 64 * RPL;
@@ -44,7 +47,8 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
     static constexpr int RW = NMAX * NW - W * NW * (NW - 1) / 2 + NMAX;   // FP64 slots per wave (bound)
     static constexpr size_t pv_elems() { return (size_t)2 * (RPL * 64 + 1); } // two pivot slots (T)
     static constexpr int NS = 8;                      // published reflector scalars per slot (FP64)
-    static constexpr size_t lds_bytes() { return ((size_t)W * RW + 2 * NS) * 8 + pv_elems() * sizeof(T); }
+    static constexpr size_t lds_bytes() { return ((size_t)(RG ? 0 : W * RW) + 2 * NS) * 8 + pv_elems() * sizeof(T); }
+    static constexpr size_t slot_bytes() { return (size_t)W * RW * 8; }   // global R of one workgroup (RG)
 
     // The W steps j = Q W + o (o = 0 .. W-1) whose pivot is local column Q of
     // wave o.  Q is a compile-time index, so the pivot is read straight from
@@ -67,6 +71,13 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                 const int c0 = Q + (wv < o ? 1 : 0); // first live local column of this wave
                 T* slot = pv + (j & 1) * (RPL * 64 + 1);
                 double* sc = apub + (j & 1) * NS;    // this step's reflector scalars
+                const int c = Q + vi;
+                const bool mine = vi < CNT && c >= c0;
+                // R(j, :) of this wave, written at step j of the previous block:
+                // from global memory (RG) it is read before the step's other
+                // work, so its latency overlaps it
+                double rj_pre = 0.0;
+                if constexpr (RG) rj_pre = mine ? Rw[off + c - c0] : 0.0;
                 if (wv == o) {
                     // The owner holds the whole pivot column: it alone forms
                     // sigma and the reflector scalars (FP64) and publishes
@@ -77,7 +88,8 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
 #pragma unroll
                     for (int r = 1; r < RPL; ++r) sg = fma_t(x[r][Q], x[r][Q], sg);
                     const double sigma = (double)wave_sum(sg);
-                    const double alpha = Rw[off];    // R(j, j): first entry of the owner's row j
+                    // R(j, j): first entry of the owner's row j (lane 0 holds local column Q)
+                    const double alpha = RG ? lane_bcast(rj_pre, 0) : Rw[off];
                     const bool lv = sigma != 0.0;
                     double beta, inv_beta, s_;
                     if constexpr (sizeof(T) == 4) {
@@ -124,10 +136,8 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
                     }
                 }
                 const T D = butterfly<PV, CNT>(p);
-                const int c = Q + vi;
-                const bool mine = vi < CNT && c >= c0;
                 const bool piv = wv == o && vi == 0;
-                const double rj = mine ? Rw[off + c - c0] : 0.0;
+                const double rj = RG ? rj_pre : (mine ? Rw[off + c - c0] : 0.0);
                 double w = __builtin_fma(s, (double)D, rj);
                 if (piv) w = -beta;
                 double rn = __builtin_fma(-tau, w, rj);
@@ -150,10 +160,11 @@ template <typename T, typename TI, int NW, int W, int RPL> struct Wide {
     }
 };
 
-// The W waves of the workgroup factor slab `sid` of `a` and store leaf node `sid`.
-template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
-__device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsigned char* smem) {
-    using S = Wide<T, TI, NW, W, RPL>;
+// The W waves of the workgroup factor slab `sid` of `a` and store leaf node
+// `sid`; with RG their R lives in global slot `rslot` of a.tree.rglob.
+template <typename T, typename TI, int NW, int W, int RPL, int LOAD, bool RG = false>
+__device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsigned char* smem, int64_t rslot = 0) {
+    using S = Wide<T, TI, NW, W, RPL, RG>;
     constexpr int P = S::P;
     // The wave index is uniform across the wave; reading it through
     // readfirstlane keeps it, the R base and the owner tests in scalar
@@ -161,8 +172,15 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int L = lane_id();
     const int n = a.n;
-    double* Rw = (double*)smem + (size_t)wv * S::RW;  // this wave's part of R (compact rows)
-    double* apub = (double*)smem + (size_t)W * S::RW;  // reflector scalars of steps j (two slots by parity)
+    double* Rw;                                        // this wave's part of R (compact rows)
+    double* apub;                                      // reflector scalars of steps j (two slots by parity)
+    if constexpr (RG) {
+        Rw = a.tree.rglob + ((size_t)rslot * W + wv) * S::RW;
+        apub = (double*)smem;
+    } else {
+        Rw = (double*)smem + (size_t)wv * S::RW;
+        apub = (double*)smem + (size_t)W * S::RW;
+    }
     T* pv = (T*)(apub + 2 * S::NS);
 
     for (int i = L; i < S::RW; i += 64) Rw[i] = 0.0;
@@ -235,7 +253,7 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
         // which the previous block's step n - 1 (n odd) may still be reading.
         if (b0 != r0) __syncthreads();
         int off = 0;                                 // start of row j in this wave's storage
-        Wide<T, TI, NW, W, RPL>::template level<0>(x, n, wv, L, Rw, apub, pv, off);
+        S::template level<0>(x, n, wv, L, Rw, apub, pv, off);
     }
     __syncthreads();
     // leaf node: row-major n x n FP64, zeros below the diagonal
@@ -255,10 +273,10 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
     if (a.tree.node_cs != nullptr && L < NW && wv + W * L < n) a.tree.node_cs[sid * n + wv + W * L] = v;
 }
 
-template <typename T, typename TI, int NW, int W, int RPL, int LOAD>
+template <typename T, typename TI, int NW, int W, int RPL, int LOAD, bool RG = false>
 __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2))) tsqr_wide_kernel(WideArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    wide_slab<T, TI, NW, W, RPL, LOAD>(a, blockIdx.x, smem);
+    wide_slab<T, TI, NW, W, RPL, LOAD, RG>(a, blockIdx.x, smem, blockIdx.x);
 }
 
 // ---- FP64 G-ary tree for wide factors -------------------------------------------
@@ -270,8 +288,9 @@ __global__ void __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(2))
 // group (by ticket) climbs; the one that produces the single top node writes R
 // (rows flipped to a nonnegative diagonal) and the column sums.  `go` is a
 // workgroup-shared flag.
-template <int NW, int W, int RPLD, int G>
-__device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t group0, unsigned char* smem, int* go) {
+template <int NW, int W, int RPLD, int G, bool RG = false>
+__device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t group0, unsigned char* smem, int* go,
+                                               int64_t rslot = 0) {
     const int tid = (int)threadIdx.x;
     const int64_t nn = (int64_t)n * n;
     int64_t group = group0, count = t.leaves, base = 0, tbase = 0;
@@ -290,7 +309,7 @@ __device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t
         a.tree = t;
         a.tree.nodes = t.nodes + (nbase + group) * nn;
         a.tree.node_cs = nullptr;
-        wide_slab<double, double, NW, W, RPLD, LOAD_ROW_BUF>(a, 0, smem);
+        wide_slab<double, double, NW, W, RPLD, LOAD_ROW_BUF, RG>(a, 0, smem, rslot);
         double* cs_out = t.node_cs + (nbase + group) * n;
         for (int c = tid; c < n; c += W * 64) {
             double s = 0.0;
@@ -333,11 +352,11 @@ __device__ __forceinline__ void wide_merge_run(const TreeArgs& t, int n, int64_t
 }
 
 
-template <int NW, int W, int RPLD, int G>
+template <int NW, int W, int RPLD, int G, bool RG = false>
 __global__ void __launch_bounds__(W * 64) tsqr_wide_merge_kernel(TreeArgs t, int n) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int go;
-    wide_merge_run<NW, W, RPLD, G>(t, n, blockIdx.x, smem, &go);
+    wide_merge_run<NW, W, RPLD, G, RG>(t, n, blockIdx.x, smem, &go, blockIdx.x);
 }
 
 }  // namespace tsnmf

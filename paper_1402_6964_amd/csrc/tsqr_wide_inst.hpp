@@ -1,4 +1,4 @@
-// Launch helper for the wide TSQR path (33..128 columns): the leaf kernel
+// Launch helper for the wide TSQR path (33..256 columns): the leaf kernel
 // over row slabs followed by the G-ary FP64 tree over the slab factors.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -14,11 +14,12 @@ namespace tsnmf {
 // cost (reflector scalars, pivot exchange, barrier) over.
 template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 11 : 5; }
 
-template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_rpl<T>()>
+template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_rpl<T>(), bool RG = false,
+          int RPLD = 4>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
-    using S = Wide<T, TI, NW, W, RPL>;
+    using S = Wide<T, TI, NW, W, RPL, RG>;
     const size_t lds = S::lds_bytes();
-    auto kern = tsqr_wide_kernel<T, TI, NW, W, RPL, LOAD>;
+    auto kern = tsqr_wide_kernel<T, TI, NW, W, RPL, LOAD, RG>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -29,10 +30,9 @@ hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     profile_split(stream);
     // FP64 tree: groups of 4 stacked factors, each factored by the wide kernel
     constexpr int G = 4;
-    constexpr int RPLD = 4;
-    using M = Wide<double, double, NW, W, RPLD>;
+    using M = Wide<double, double, NW, W, RPLD, RG>;
     const size_t mlds = M::lds_bytes();
-    auto mk = tsqr_wide_merge_kernel<NW, W, RPLD, G>;
+    auto mk = tsqr_wide_merge_kernel<NW, W, RPLD, G, RG>;
     if (mlds > 65536) {
         e = hipFuncSetAttribute((const void*)mk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
         if (e != hipSuccess) return e;
@@ -40,6 +40,22 @@ hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     const int64_t groups = (a.tree.leaves + G - 1) / G;
     hipLaunchKernelGGL(mk, dim3((unsigned)groups), dim3(W * 64), mlds, stream, a.tree, a.n);
     return hipGetLastError();
+}
+
+// 129..256 columns: 8 waves x 32 columns, R of each workgroup in a global
+// slot (a.tree.rglob, one per leaf workgroup; the tree's workgroups reuse the
+// first ones after the leaves are done).  Every R slot holds
+// xl_slot_bytes() bytes.
+constexpr int kXlRplF32 = 4;
+constexpr int kXlRplF64 = 2;
+constexpr size_t xl_slot_bytes() {
+    return Wide<float, float, 32, 8, kXlRplF32, true>::slot_bytes() > Wide<double, double, 32, 8, kXlRplF64, true>::slot_bytes()
+               ? Wide<float, float, 32, 8, kXlRplF32, true>::slot_bytes()
+               : Wide<double, double, 32, 8, kXlRplF64, true>::slot_bytes();
+}
+template <typename T, typename TI, int LOAD>
+hipError_t launch_wide_xl(const WideArgs& a, hipStream_t stream) {
+    return launch_wide_w<T, TI, 8, LOAD, 32, sizeof(T) == 4 ? kXlRplF32 : kXlRplF64, true, kXlRplF64>(a, stream);
 }
 
 }  // namespace tsnmf

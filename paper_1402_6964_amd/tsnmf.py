@@ -29,7 +29,8 @@ COL_MAJOR = 0x10
 LEAF_F64 = 0x20
 GP_MFMA_BF16 = 0x100
 GP_SIMD_F32 = 0x200
-MAX_N = 128
+MAX_N = 256
+MAX_BATCH_N = 128
 MAX_BATCH = 4096
 
 _vp = ctypes.c_void_p
@@ -43,11 +44,24 @@ class TsqrConfig(ctypes.Structure):
     _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32)]
 
 
+class _Entry:
+    """A C entry point, resolved in the library on its first call (a symbol the
+    library lacks raises AttributeError there, naming the function)."""
+
+    def __init__(self, name, res, args):
+        self.name, self.res, self.args, self.f = name, res, args, None
+
+    def __call__(self, *a):
+        if self.f is None:
+            f = getattr(_lib, self.name)
+            f.restype = self.res
+            f.argtypes = self.args
+            self.f = f
+        return self.f(*a)
+
+
 def _sig(name, res, args):
-    f = getattr(_lib, name)
-    f.restype = res
-    f.argtypes = args
-    return f
+    return _Entry(name, res, args)
 
 
 _tsqr_r = _sig("tsnmf_tsqr_r", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
@@ -64,6 +78,7 @@ _nnls = _sig("tsnmf_nnls", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp,
 _residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
 _reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
 _workspace_release = _sig("tsnmf_workspace_release", ctypes.c_int, [])
+_tune_load = _sig("tsnmf_tune_load", ctypes.c_int, [ctypes.c_char_p])
 _profile_enable = _sig("tsnmf_profile_enable", ctypes.c_int, [ctypes.c_int])
 _profile_query = _sig("tsnmf_profile_query", ctypes.c_int,
                       [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)])
@@ -155,6 +170,10 @@ def tsnmf_workspace_release():
     return _workspace_release()
 
 
+def tsnmf_tune_load(path):
+    return _tune_load(None if path is None else os.fsencode(path))
+
+
 def tsnmf_profile_enable(on):
     """on: 0/False off, 1/True every stage, 2 the main kernel only."""
     return _profile_enable(on if on in (0, 1, 2) and not isinstance(on, bool) else (1 if on else 0))
@@ -213,8 +232,7 @@ def tsqr_r(X, leaf_f64=False, config=None, stream=None, with_colsum=True):
         if config != "tuned":
             raise ValueError("config must be None, a TsqrConfig or 'tuned'")
         from . import tune
-        dt = {torch.float32: "f32", torch.float64: "f64"}.get(X.dtype, "other")
-        config = tune.lookup(dt, "col" if lay == COL_MAJOR else "row", n, m)
+        config = tune.lookup(X, leaf_f64)
     flags = _DTYPE_FLAG[X.dtype] | lay | (LEAF_F64 if leaf_f64 else 0)
     Rbuf = torch.empty((n, n), dtype=torch.float64, device=X.device)
     cs = torch.empty(n, dtype=torch.float64, device=X.device) if with_colsum else None

@@ -1,19 +1,25 @@
 """Autotuner for the TSQR launch geometry (leaf height and tree arity).
 
-    python -m paper_1402_6964_amd.tune --m 10000000 --n 25 [--dtype f32] [--layout row]
+    python -m paper_1402_6964_amd.tune --m 10000000 --n 25 [--dtype f32] [--layout row] [--leaf f32] [--pad 0]
 
 For one input shape it times tsnmf_tsqr_r_ex over a grid of leaf heights
-(rows per slab) and, for n <= 32, tree group sizes (slab factors merged per
-tree node) with HIP events.  It rejects any configuration whose R differs
-from the default configuration's by more than the rounding bound of the
-precision used (every configuration computes the same R up to rounding), and
-records the fastest in paper_1402_6964_amd/tuned.json, keyed by
-(dtype, layout, n, floor(log2 m)).  tsnmf.tsqr_r(X, config="tuned") applies
-the recorded entry for X's key (the library default when there is none).
+(rows per slab, the TSQR leaf) and, for n <= 32, tree group sizes (slab
+factors merged per tree node) with HIP events.  It rejects any configuration
+whose R differs from the default configuration's by more than the rounding
+bound of the precision used (every configuration computes the same R up to
+rounding), and records the fastest in the text table
+paper_1402_6964_amd/tuned.txt, keyed like the library's table by (input
+dtype, layout, row-block precision, contiguous rows, n, floor(log2 m)).
+tsnmf_tune_load(path) makes the library apply it to every tsnmf_tsqr_r call
+that matches an entry; tsnmf.tsqr_r(X, config="tuned") applies the entry for
+X explicitly.
+
+The row-block height (rows one wave holds in registers per Householder pass)
+is a compile-time constant per width, chosen by measurement; the tunable
+"leaf height" of the TSQR is the slab, which is a runtime parameter.
 """
 
 import argparse
-import json
 import math
 import os
 
@@ -21,32 +27,61 @@ import torch
 
 from . import synth, tsnmf
 
-TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.txt")
+HEADER = ("# tsnmf autotune table: tsqr <dtype> <layout> <leaf precision> <ld == n> <n> <floor(log2 m)> "
+          "<leaf_rows> <tree_arity>\n")
 
 
-def key(dtype, layout, n, m):
-    return f"{dtype}:{layout}:{n}:{int(math.log2(max(m, 1)))}"
+def key(dtype, layout, leaf, ldeq, n, m):
+    return (dtype, layout, leaf, int(bool(ldeq)), int(n), int(math.log2(max(m, 1))))
 
 
-def load():
+def load(path=None):
+    """The table as {key: (leaf_rows, tree_arity, comment)}."""
+    out = {}
     try:
-        with open(TUNED) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
+        with open(path or TUNED) as f:
+            for line in f:
+                body, _, note = line.partition("#")
+                p = body.split()
+                if len(p) != 9 or p[0] != "tsqr":
+                    continue
+                k = (p[1], p[2], p[3], int(p[4]), int(p[5]), int(p[6]))
+                out[k] = (int(p[7]), int(p[8]), note.strip())
+    except OSError:
+        pass
+    return out
 
 
-def lookup(dtype, layout, n, m):
-    e = load().get(key(dtype, layout, n, m))
-    if e is None:
-        return None
-    return tsnmf.TsqrConfig(leaf_rows=int(e["leaf_rows"]), tree_arity=int(e.get("tree_arity", 0)), rows_per_lane=0)
+def save(table, path=None):
+    with open(path or TUNED, "w") as f:
+        f.write(HEADER)
+        for k in sorted(table):
+            leaf_rows, arity, note = table[k]
+            f.write(f"tsqr {k[0]} {k[1]} {k[2]} {k[3]} {k[4]} {k[5]} {leaf_rows} {arity}"
+                    + (f"  # {note}" if note else "") + "\n")
 
 
-def time_config(X, cfg, reps=20):
+def key_of(X, leaf_f64=False):
     m, n = X.shape
     lay, ld = tsnmf._layout(X)
-    flags = tsnmf._DTYPE_FLAG[X.dtype] | lay
+    dt = {torch.float32: "f32", torch.float64: "f64"}[X.dtype]
+    col = lay == tsnmf.COL_MAJOR
+    leaf = "f64" if (dt == "f64" or leaf_f64) else "f32"
+    return key(dt, "col" if col else "row", leaf, ld == (m if col else n), n, m)
+
+
+def lookup(X, leaf_f64=False, path=None):
+    e = load(path).get(key_of(X, leaf_f64))
+    if e is None:
+        return None
+    return tsnmf.TsqrConfig(leaf_rows=e[0], tree_arity=e[1], rows_per_lane=0)
+
+
+def time_config(X, cfg, leaf_f64=False, reps=20):
+    m, n = X.shape
+    lay, ld = tsnmf._layout(X)
+    flags = tsnmf._DTYPE_FLAG[X.dtype] | lay | (tsnmf.LEAF_F64 if leaf_f64 else 0)
     Rbuf = torch.empty((n, n), dtype=torch.float64, device=X.device)
     cs = torch.empty(n, dtype=torch.float64, device=X.device)
     for _ in range(3):
@@ -60,23 +95,28 @@ def time_config(X, cfg, reps=20):
     return ev0.elapsed_time(ev1) / reps, Rbuf.t().cpu()
 
 
-def tune(X, leaf_grid=None, arity_grid=None, verbose=True):
+def leaf_grid(m):
+    """Leaf heights around the default's: slabs for 512 .. 4096 leaves, and the
+    fixed heights 256, 512 and 1024 rows (lengthened by the library where the
+    leaf count would exceed its ticket area)."""
+    return [0] + sorted({max(64, m // p) for p in (512, 1024, 1536, 2048, 3072, 4096)} | {256, 512, 1024})
+
+
+def tune(X, leaf_f64=False, grid=None, arity_grid=None, verbose=True):
     m, n = X.shape
-    lay, _ = tsnmf._layout(X)
-    t0, R0 = time_config(X, None)
-    tol = 1e-5 if X.dtype == torch.float32 else 1e-11
-    if leaf_grid is None:
-        leaf_grid = [0] + sorted({max(64, m // p) for p in (256, 512, 1024, 1536, 2048, 3072, 4096)})
+    t0, R0 = time_config(X, None, leaf_f64)
+    tol = 1e-5 if (X.dtype == torch.float32 and not leaf_f64) else 1e-11
+    grid = leaf_grid(m) if grid is None else grid
     if arity_grid is None:
         arity_grid = [0, 8, 12, 16, 20, 24, 32] if n <= 32 else [0]
     best = (t0, 0, 0)
     results = [{"leaf_rows": 0, "tree_arity": 0, "ms": t0}]
-    for leaf in leaf_grid:
+    for leaf in grid:
         for ar in arity_grid:
             if leaf == 0 and ar == 0:
                 continue
             cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=int(ar), rows_per_lane=0)
-            ms, R = time_config(X, cfg)
+            ms, R = time_config(X, cfg, leaf_f64)
             err = float((R - R0).abs().max() / R0.abs().max())
             ok = err <= tol
             results.append({"leaf_rows": int(leaf), "tree_arity": int(ar), "ms": ms, "err": err, "ok": ok})
@@ -85,10 +125,8 @@ def tune(X, leaf_grid=None, arity_grid=None, verbose=True):
                       f"{m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}", flush=True)
             if ok and ms < best[0]:
                 best = (ms, int(leaf), int(ar))
-    dt = {torch.float32: "f32", torch.float64: "f64"}[X.dtype]
-    lname = "col" if lay == tsnmf.COL_MAJOR else "row"
-    entry = {"leaf_rows": best[1], "tree_arity": best[2], "ms": best[0], "default_ms": t0}
-    return key(dt, lname, n, m), entry, results
+    note = f"{best[0]:.4f} ms against {t0:.4f} ms default"
+    return key_of(X, leaf_f64), (best[1], best[2], note), results
 
 
 def main():
@@ -97,20 +135,21 @@ def main():
     ap.add_argument("--n", type=int, default=25)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--layout", choices=["row", "col"], default="row")
+    ap.add_argument("--leaf", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--pad", type=int, default=0, help="extra elements of the row stride (row-major)")
     ap.add_argument("--no-save", action="store_true")
     args = ap.parse_args()
     dt = torch.float32 if args.dtype == "f32" else torch.float64
     if args.layout == "row":
-        X = synth.random_matrix(args.m, args.n, device="cuda", dtype=dt, seed_tag=11)
+        X = synth.random_matrix(args.m, args.n + args.pad, device="cuda", dtype=dt, seed_tag=11)[:, :args.n]
     else:
         X = synth.random_matrix(args.n, args.m, device="cuda", dtype=dt, seed_tag=11).t()
-    k, best, _ = tune(X)
-    print(json.dumps({k: best}))
+    k, best, _ = tune(X, leaf_f64=args.leaf == "f64")
+    print(k, best)
     if not args.no_save:
         table = load()
         table[k] = best
-        with open(TUNED, "w") as f:
-            json.dump(table, f, indent=1, sort_keys=True)
+        save(table)
 
 
 if __name__ == "__main__":

@@ -162,7 +162,7 @@ def test_gaussian_entries_bf16(lib, offset):
 # ---- Y, entry by entry -------------------------------------------------------------
 
 @pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (20_000, 1, 8), (33_333, 7, 512), (40_001, 128, 512),
-                                   (3, 5, 4), (100, 128, 1028)])
+                                   (3, 5, 4), (100, 128, 1028), (30_001, 200, 64), (10_000, 256, 516)])
 def test_simd_fp32_matches_oracle(lib, m, n, k):
     X = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=31, dist="lognormal")
     Yg, csg = _gp(lib, X.cuda(), k, 14026964, mode=lib.GP_SIMD_F32, colsum=True)
@@ -175,7 +175,8 @@ def test_simd_fp32_matches_oracle(lib, m, n, k):
     assert np.max(np.abs(csg - d) / d) <= 1e-12
 
 
-@pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (33_333, 128, 512), (1000, 3, 1028)])
+@pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (33_333, 128, 512), (1000, 3, 1028), (20_000, 256, 128),
+                                   (5_000, 130, 64)])
 def test_mfma_bf16_matches_oracle(lib, m, n, k):
     X32 = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=32, dist="uniform")
     Xb = X32.to(torch.bfloat16)

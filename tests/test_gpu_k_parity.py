@@ -157,6 +157,9 @@ def test_projection_k(lib, mode):
     row_err = np.abs(Yn - Yon).max(axis=1) / np.abs(Yon).max(axis=1)
     amb = gp_row_margins(Yo, do) <= 2 * row_err
     Kg, cg, _ = lib.select_gp(Yg, r, colscale=csg)
+    # the selection kernel itself: bit-identical to the oracle on the same Y
+    Kgh, cgh, _ = osel.gp_select(Yh, r, colscale=csg.cpu().numpy())
+    assert Kg.cpu().tolist() == Kgh and np.array_equal(cg.cpu().numpy(), cgh)
     Kgo, cgo, _ = osel.gp_select(Yo, r, colscale=do)
     print(f"{mode}: Y error {e:.2e}; GP K = {Kg.cpu().tolist()}; ambiguous rows {int(amb.sum())}")
     cg = cg.cpu().numpy()
@@ -169,13 +172,23 @@ def test_projection_k(lib, mode):
         srt = np.sort(np.asarray(cgo))[::-1]
         assert srt[r - 1] - srt[r] > 2 * na          # the set is decided regardless
         assert sorted(Kg.cpu().tolist()) == sorted(Kgo)
-    # SPA on the projection, normalised by the column sums
+    # SPA on the projection, normalised by the column sums.  The SPA kernel on
+    # the GPU's Y equals the oracle's SPA on the same Y (FP64 margins far
+    # above its rounding); the projection's error may change a pick only where
+    # the oracle's margin is within a few times that error: the selections
+    # agree up to the first such pick, and entirely when there is none.
+    Ks = _gpu_spa(lib, Yg.double(), csg, r)
+    Ksh, _, _ = osel.spa(Yh, r, colscale=csg.cpu().numpy())
+    assert spa_margins(Yh, Ksh, csg.cpu().numpy()).min() > 1e-9
+    assert Ks == Ksh
     Kso, _, _ = osel.spa(Yo, r, colscale=do)
     mg = spa_margins(Yo, Kso, do)
-    Ks = _gpu_spa(lib, Yg.double(), csg, r)
-    print(f"{mode}: SPA K = {Ks}; smallest margin {mg.min():.2e}")
-    assert mg.min() > 20 * e
-    assert Ks == Kso
+    near = np.flatnonzero(mg <= 4 * e)
+    first = int(near[0]) if near.size else r
+    print(f"{mode}: SPA K = {Ks}; smallest margin {mg.min():.2e}; first pick within 4 e: {first}")
+    assert Ks[:first] == Kso[:first]
+    if first == r:
+        assert sorted(Ks) == d["K"]
 
 
 @pytest.mark.timeout(600)

@@ -186,18 +186,36 @@ def test_pipeline_flow_cytometry_fp32(lib):
     assert np.abs(H.cpu().numpy() - Ho).max() <= 1e-4 * np.abs(Ho).max()
 
 
-def test_paper_example_selection_on_gpu(lib):
-    """Sec. 4 example at m = 20,000 (n = 200, beyond the TSQR width limit): the
-    oracle's R and column sums feed the GPU selection and NNLS; SPA recovers
-    {0, 1, 20, ..., 190} and the residual at r = 20 vanishes."""
-    d = synth.paper_example(20_000)
-    Xh = d["X"].numpy()
-    R = otsqr.tsqr_r_final(Xh, leaf_rows=1000)
-    dsum = np.abs(Xh).sum(0)
-    K, _, _ = lib.select_spa(_cuda(R), 20, colscale=_cuda(dsum))
-    assert sorted(K.cpu().tolist()) == d["K"]
-    H, _, _ = lib.nnls(_cuda(R), K)
-    rel = lib.residual(_cuda(R), K, H)
-    assert rel.item() < 1e-20
-    Kx, _ = lib.select_xray(_cuda(R), 21)
+@pytest.mark.parametrize("noisy", [False, True])
+def test_paper_example_end_to_end_on_gpu(lib, noisy):
+    """The Sec. 4 example at m = 20,000 (n = 200, r = 20; exactly separable, and
+    with U[0, 1e-3] noise), the whole path on the GPU: TSQR with column sums
+    (FP64, 200 columns), SPA on R D^{-1}, NNLS and the residual.  Against the
+    oracle on the same bytes: the same K, equal to the swap rule's
+    {0, 1, 20, 30, ..., 190}; the residual vanishes at r = 20 on exact data and
+    is at the noise level otherwise; the first 21 greedy XRAY picks contain K."""
+    d = synth.paper_example(20_000, noisy=noisy)
+    X = d["X"]
+    R, cs = lib.tsqr_r(X.cuda())
+    K, _, info = lib.select_spa(R, 20, colscale=cs)
+    H, _, _ = lib.nnls(R, K)
+    rel = lib.residual(R, K, H)
+    torch.cuda.synchronize()
+    Xh = X.numpy()
+    Ro = otsqr.tsqr_r_final(Xh, leaf_rows=1000)
+    do = np.abs(Xh).sum(0)
+    Ko, _, _ = osel.spa(Ro, 20, colscale=do)
+    assert int(info.item()) == 20
+    assert K.cpu().tolist() == Ko
+    assert sorted(Ko) == d["K"] == [0, 1] + list(range(20, 200, 10))
+    Xg = Xh.T @ Xh
+    Rg = R.cpu().numpy()
+    assert np.linalg.norm(Rg.T @ Rg - Xg) / np.trace(Xg) <= 1e-12
+    if noisy:
+        Ho, _, _ = onnls.nnls_matrix(Ro, Ko)
+        ro = ores.relative_residual(Ro, Ko, Ho)
+        assert 0.0 < rel.item() <= 1e-6 and abs(rel.item() - ro) <= 1e-3 * ro
+    else:
+        assert rel.item() < 1e-20
+    Kx, _ = lib.select_xray(R, 21)
     assert set(d["K"]) <= set(Kx.cpu().tolist())

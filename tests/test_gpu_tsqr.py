@@ -433,3 +433,31 @@ def test_graph_capture_single_calls_survive_growth(lib):
     _check_against_oracle(R.t().cpu().numpy(), cs.cpu().numpy(), X.cpu().numpy(), 1e-6, 2e-5, 1e-6, norm_tol=1e-5)
     del g
     assert lib.tsnmf_workspace_release() == 0
+
+
+@pytest.mark.parametrize("n,layout,dt", [(129, "row", torch.float32), (200, "col", torch.float32),
+                                         (256, "row", torch.float32), (256, "padded", torch.float32),
+                                         (160, "row", torch.float64), (256, "col", torch.float64)])
+def test_widest_paths(lib, n, layout, dt):
+    """129..256 columns (8 waves x 32 columns, R of each workgroup in global
+    memory): R against the oracle at the precision's tolerances, for FP32 and
+    FP64 input, row-major, column-major and a padded row stride."""
+    m = 50_011
+    X, _ = _layout_view(None, m, n, layout, dt, 500 + n)
+    Rg, csg = _run(lib, X)
+    if dt == torch.float32:
+        _check_against_oracle(Rg, csg, X.cpu().numpy(), 1e-6, 2e-5, 1e-6, norm_tol=1e-5)
+    else:
+        _check_against_oracle(Rg, csg, X.cpu().numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
+
+
+def test_widest_fp32_input_fp64_leaves_and_short(lib):
+    X = synth.random_matrix(30_007, 180, dtype=torch.float32, seed_tag=510, dist="uniform").cuda()
+    Rg, csg = _run(lib, X, leaf_f64=True)
+    _check_against_oracle(Rg, csg, X.cpu().numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)
+    for m in (1, 100, 256, 257):
+        Xs = synth.random_matrix(m, 256, dtype=torch.float32, seed_tag=511, dist="uniform").cuda()
+        Rg, csg = _run(lib, Xs)
+        X64 = Xs.cpu().numpy().astype(np.float64)
+        assert np.all(np.tril(Rg, -1) == 0.0) and np.all(np.diag(Rg) >= 0.0)
+        assert _rel_gram(Rg, X64) <= 1e-6

@@ -1,35 +1,81 @@
-"""Host logic of the autotuner's table (no GPU): keys and lookups."""
+"""Host logic of the autotuner's table (no GPU): keys, the text format the
+library reads, lookups, and the library's own parser (tsnmf_tune_load)."""
 
-import json
+import ctypes
+import os
 
 import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1402_6964_amd", "libtsnmf.so")
 
 
 @pytest.fixture()
 def tune(tmp_path, monkeypatch):
     from paper_1402_6964_amd import tune as t
-    monkeypatch.setattr(t, "TUNED", str(tmp_path / "tuned.json"))
+    monkeypatch.setattr(t, "TUNED", str(tmp_path / "tuned.txt"))
     return t
 
 
 def test_key_buckets_by_log2_rows(tune):
-    assert tune.key("f32", "row", 25, 10_000_000) == "f32:row:25:23"
-    assert tune.key("f32", "row", 25, 2 ** 23) == tune.key("f32", "row", 25, 2 ** 24 - 1)
-    assert tune.key("f64", "col", 64, 1) == "f64:col:64:0"
+    assert tune.key("f32", "row", "f32", 1, 25, 10_000_000) == ("f32", "row", "f32", 1, 25, 23)
+    assert tune.key("f32", "row", "f32", 1, 25, 2 ** 23) == tune.key("f32", "row", "f32", 1, 25, 2 ** 24 - 1)
+    assert tune.key("f64", "col", "f64", 0, 64, 1)[-1] == 0
 
 
-def test_lookup_missing_and_present(tune):
-    assert tune.lookup("f32", "row", 25, 10_000_000) is None
-    with open(tune.TUNED, "w") as f:
-        json.dump({"f32:row:25:23": {"leaf_rows": 4883, "tree_arity": 16, "ms": 0.4}}, f)
-    cfg = tune.lookup("f32", "row", 25, 10_000_000)
-    assert (cfg.leaf_rows, cfg.tree_arity, cfg.rows_per_lane) == (4883, 16, 0)
-    with open(tune.TUNED, "w") as f:
-        json.dump({"f32:row:25:23": {"leaf_rows": 1000, "ms": 0.4}}, f)   # entries without an arity
-    assert tune.lookup("f32", "row", 25, 10_000_000).tree_arity == 0
+def test_save_and_load_round_trip(tune):
+    t = {("f32", "row", "f32", 1, 25, 23): (4883, 16, "0.40 ms"),
+         ("f32", "row", "f64", 0, 25, 23): (1000, 0, "")}
+    tune.save(t)
+    assert tune.load() == t
+    txt = open(tune.TUNED).read()
+    assert "tsqr f32 row f32 1 25 23 4883 16" in txt and "tsqr f32 row f64 0 25 23 1000 0" in txt
+
+
+def test_leaf_precision_and_contiguity_are_separate_keys(tune):
+    """An entry measured on FP32 row blocks is not applied to the FP64-leaf
+    kernels, nor to strided rows."""
+    tune.save({("f32", "row", "f32", 1, 25, 23): (4883, 16, "")})
+    tab = tune.load()
+    assert ("f32", "row", "f64", 1, 25, 23) not in tab
+    assert ("f32", "row", "f32", 0, 25, 23) not in tab
 
 
 def test_unreadable_table_is_empty(tune):
     with open(tune.TUNED, "w") as f:
-        f.write("not json")
+        f.write("not a table\n")
     assert tune.load() == {}
+
+
+def _lib():
+    so = ctypes.CDLL(LIB)
+    so.tsnmf_tune_load.restype = ctypes.c_int
+    so.tsnmf_tune_load.argtypes = [ctypes.c_char_p]
+    return so
+
+
+def test_library_parser_accepts_the_table_and_rejects_bad_lines(tmp_path):
+    so = _lib()
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\n\ntsqr f32 row f32 1 25 23 4883 16  # 0.40 ms\ntsqr f64 col f64 0 64 20 0 0\n")
+    assert so.tsnmf_tune_load(str(good).encode()) == 0
+    for bad in ("tsqr f32 row f32 1 25 23 4883\n",        # missing field
+                "tsqr f16 row f32 1 25 23 4883 16\n",     # dtype
+                "tsqr f64 row f32 1 25 23 0 0\n",         # FP64 input with FP32 leaves
+                "tsqr f32 row f32 1 500 23 0 0\n",        # width
+                "tsqr f32 row f32 1 25 23 0 1\n",         # arity 1
+                "batch s16 4096\n"):                      # unknown kind
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        assert so.tsnmf_tune_load(str(p).encode()) == -1, bad
+    assert so.tsnmf_tune_load(str(tmp_path / "missing.txt").encode()) == -1
+    assert so.tsnmf_tune_load(None) == 0
+
+
+def test_committed_table_parses(tune):
+    """The table shipped with the package is read by the library."""
+    path = os.path.join(ROOT, "paper_1402_6964_amd", "tuned.txt")
+    if not os.path.exists(path):
+        pytest.skip("no tuned table committed")
+    assert _lib().tsnmf_tune_load(path.encode()) == 0
+    assert _lib().tsnmf_tune_load(None) == 0

@@ -104,6 +104,24 @@ extern "C" {
 int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
                  double* R, double* colsum, hipStream_t stream);
 
+/*
+ * tsnmf_tsqr_r_noalloc: tsnmf_tsqr_r for callers that cannot allocate device
+ * memory (code under graph capture that has not reserved, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and error
+ * codes; it calls no hipMalloc, hipFree or allocating routine.  Its tickets
+ * and tree nodes live in a fixed 32 MiB scratch array that the library holds
+ * on every device it runs on until the process ends; when the default slabs
+ * would need a larger tree, the slabs are lengthened (fewer leaves) until the
+ * tree fits, so R equals tsnmf_tsqr_r's up to rounding.  A shape whose tree
+ * still cannot fit returns TSNMF_ERR_UNSUPPORTED (not reachable for
+ * n <= TSNMF_MAX_N).  All calls on one device share that array: calls that
+ * overlap on one device (other streams, other threads) race and must not be
+ * made.  The first call on a device clears the array's ticket area on
+ * `stream`.
+ */
+int tsnmf_tsqr_r_noalloc(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
+                         double* R, double* colsum, hipStream_t stream);
+
 /* Launch geometry of the TSQR path.  Zero fields mean "library default". */
 typedef struct tsnmf_tsqr_config {
     int64_t leaf_rows;      /* rows per slab (the TSQR leaf); a slab that is not

@@ -178,6 +178,22 @@ int tsnmf_tsqr_r(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags
     return tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum, have ? &tuned : nullptr, stream);
 }
 
+int tsnmf_tsqr_r_noalloc(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags, double* R,
+                         double* colsum, hipStream_t stream) {
+    if (X == nullptr) return -1;
+    if (m < 1) return -2;
+    if (n < 1) return -3;
+    const uint32_t dt = flags & TSNMF_DTYPE_MASK;
+    const bool col = (flags & TSNMF_COL_MAJOR) != 0;
+    if (ld < (col ? m : n)) return -4;
+    if ((dt != TSNMF_F32 && dt != TSNMF_F64) ||
+        (flags & ~(TSNMF_DTYPE_MASK | TSNMF_COL_MAJOR | TSNMF_LEAF_F64)) != 0)
+        return -5;
+    if (R == nullptr) return -6;
+    if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
+    return tsqr_r_noalloc_impl(X, m, (int)n, ld, flags, R, colsum, stream);
+}
+
 int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
                          const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
                          hipStream_t stream) {

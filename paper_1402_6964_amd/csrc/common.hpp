@@ -71,5 +71,7 @@ int batch_reserve(int32_t max_batch, int64_t max_rows);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
                 double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream, void* fixed_ws = nullptr,
                 size_t fixed_bytes = 0);
+int tsqr_r_noalloc_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R, double* colsum,
+                        hipStream_t stream);
 
 }  // namespace tsnmf

@@ -178,6 +178,54 @@ int64_t fixed_leaves(int n, size_t bytes) {
 // at most kTargetStreams leaves, and at most m: size the tree for that many.
 size_t tsqr_workspace_bytes(int64_t m, int n) { return tree_bytes(std::min<int64_t>(m, kTargetStreams), n); }
 
+// ---- allocation-free variant: a fixed scratch array per device ----------------
+//
+// tsnmf_tsqr_r_noalloc keeps its tickets and tree nodes in this array instead
+// of the grown workspace, so it never allocates.  In host code `scratch` is
+// only a stand-in for the symbol: its device address (one per GPU) comes from
+// hipGetSymbolAddress at the first call on each device and is kept in
+// g_scratch; only that address is ever handed to kernels.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch;       // device address of `scratch`, per device
+
+__global__ void zero_words_kernel(int* p, int count) {
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < count; i += (int)(gridDim.x * blockDim.x))
+        p[i] = 0;
+}
+
+// The scratch address of the current device; at its first use the ticket
+// area is cleared (by a kernel on `stream`: the array is zero when the code
+// object loads, and every call leaves its tickets zero again).
+int scratch_get(hipStream_t stream, void** out) {
+    int dev = 0;
+    TSNMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+    if (g_scratch[dev] == nullptr) {
+        void* p = nullptr;
+        TSNMF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        hipLaunchKernelGGL(zero_words_kernel, dim3(64), dim3(256), 0, stream, (int*)p,
+                           (int)(kTicketBytes / sizeof(int)));
+        TSNMF_LAUNCH_CHECK();
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return TSNMF_OK;
+}
+
+}  // namespace
+
+int tsqr_r_noalloc_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R, double* colsum,
+                        hipStream_t stream) {
+    void* ws = nullptr;
+    if (int st = scratch_get(stream, &ws)) return st;
+    return tsqr_r_impl(X, m, n, ld, flags, R, colsum, nullptr, stream, ws, kScratchBytes);
+}
+
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
                 double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream, void* fixed_ws,
                 size_t fixed_bytes) {

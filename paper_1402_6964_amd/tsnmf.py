@@ -65,6 +65,7 @@ def _sig(name, res, args):
 
 
 _tsqr_r = _sig("tsnmf_tsqr_r", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
+_tsqr_r_noalloc = _sig("tsnmf_tsqr_r_noalloc", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
 _tsqr_r_ex = _sig("tsnmf_tsqr_r_ex", ctypes.c_int,
                   [_vp, _i64, _i64, _i64, _u32, _vp, _vp, ctypes.POINTER(TsqrConfig), _vp])
 _tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp])
@@ -122,6 +123,10 @@ def _check(fn, st):
 
 def tsnmf_tsqr_r(X, m, n, ld, flags, R, colsum=None, stream=None):
     return _tsqr_r(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), _stream(stream))
+
+
+def tsnmf_tsqr_r_noalloc(X, m, n, ld, flags, R, colsum=None, stream=None):
+    return _tsqr_r_noalloc(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), _stream(stream))
 
 
 def tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):

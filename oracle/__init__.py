@@ -17,6 +17,10 @@ Modules
     philox      Philox4x32-10 counter-based generator + Box-Muller normals,
                 restated from Salmon et al. (SC'11), used as G of Sec. 2.3.
     gauss_proj  Y = G^T X accumulated row by row (Algorithm 1, Sec. 3.2).
+    rsvd        singular values and vectors of R (Sec. 3.1, R-SVD) and the
+                residual curve over candidate ranks r (Sec. 2.2, Sec. 2.4).
+    parallel    the same leaf factors and tree, with runs of leaves in worker
+                processes (used to time the oracle on every host core).
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against facts the
 paper and the mathematics fix (LAPACK on tiny inputs, closed forms such as the
@@ -25,4 +29,4 @@ KKT conditions, rocRAND's Philox rounds).  No function here is "parity
 unpinned".
 """
 
-from . import tsqr, select, nnls, residual, philox, gauss_proj  # noqa: F401
+from . import tsqr, select, nnls, residual, philox, gauss_proj, rsvd  # noqa: F401

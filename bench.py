@@ -40,12 +40,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ALU_PEAK_TFLOPS = 78.6      # FP32 FMA, vector ALUs, packed instructions disabled
+FP32_VECTOR_PEAK = 157.3    # FP32 vector/matrix peak of MI355X (256 CUs x 2.4 GHz, packed FP32)
+FP32_UNPACKED_PEAK = 78.6   # FP32 FMA on the vector ALUs without packed instructions (this build)
 METRIC = "TSQR GB/s of X (fraction of HBM peak) + batched matrices/s at fixed R error"
 WORKLOAD = {"workload": "flow_cytometry", "m": 10_000_000, "n": 25, "dtype_in": "fp32",
             "layout": "row-major", "bytes": 10_000_000 * 25 * 4, "r": 16}
 LEAF_KERNEL = "tsqr_small_kernel<float, float, 25, 6, 1>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tsqr_leaf_flow_cytometry.md")
+TUNED_FILE = os.path.join(ROOT, "paper_1402_6964_amd", "tuned.txt")
 
 
 def parse_args():
@@ -143,6 +145,18 @@ def cpu_baseline(X_gpu, R_gpu, cs_gpu, target_s, pool):
     return out
 
 
+def geometry(tuned, dt, lay, leaf, ldeq, n, m):
+    """The launch geometry tsnmf_tsqr_r uses for this key: the tuned entry, or
+    the library default."""
+    import math
+    if tuned:
+        e = tuned.get((dt, lay, leaf, ldeq, n, int(math.log2(max(m, 1)))))
+        if e is not None:
+            return {"source": "tuned.txt", "leaf_rows": e[0], "tree_arity": e[1], "wy_panel": e[2],
+                    "note": e[3]}
+    return {"source": "library default"}
+
+
 def _note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -162,7 +176,7 @@ def _gram_error(R, X64):
     return float(np.linalg.norm(R.T @ R - G) / np.trace(G))
 
 
-def extras(torch, tsnmf, synth, dev, check=True):
+def extras(torch, tsnmf, synth, dev, check=True, tuned=None):
     """The other hot-path workloads, a few timed repetitions each."""
     import numpy as np
     out = {}
@@ -238,17 +252,35 @@ def extras(torch, tsnmf, synth, dev, check=True):
         if st != 0:
             raise tsnmf.TsnmfError("tsnmf_tsqr_r", st)
 
-    heat()
-    tsnmf.tsnmf_profile_query(0)
-    tsnmf.tsnmf_profile_enable(2)
-    t = _timed(torch, heat, 5)
-    tsnmf.tsnmf_profile_enable(0)
-    _, lms, lcalls = tsnmf.tsnmf_profile_query(0)
-    tsnmf.tsnmf_profile_query(1)
     hb = m * n * 4
-    out["heat_transfer"] = {"workload": "50,000,000 x 64 FP32 column-major (12.8 GB)", "ms": round(t * 1e3, 3),
-                            "gbs": round(hb / t / 1e9, 1),
-                            "leaf_gbs": round(hb / (lms / max(lcalls, 1) * 1e-3) / 1e9, 1)}
+    hflops = 2.0 * m * n * n
+    out["heat_transfer"] = {"workload": "50,000,000 x 64 FP32 column-major (12.8 GB)",
+                            "geometry": geometry(tuned, "f32", "col", "f32", 1, n, m)}
+    # the library's choice (tsnmf_tsqr_r), and the blocked compact-WY and
+    # unblocked leaves side by side (tsnmf_tsqr_r_ex)
+    for name, cfg in (("default", None),
+                      ("wy16", tsnmf.TsqrConfig(leaf_rows=0, tree_arity=0, rows_per_lane=0, wy_panel=16)),
+                      ("unblocked", tsnmf.TsqrConfig(leaf_rows=0, tree_arity=0, rows_per_lane=0, wy_panel=1))):
+        def heat():
+            if cfg is None:
+                st = tsnmf.tsnmf_tsqr_r(X, m, n, m, tsnmf.F32 | tsnmf.COL_MAJOR, R, c, stream)
+            else:
+                st = tsnmf.tsnmf_tsqr_r_ex(X, m, n, m, tsnmf.F32 | tsnmf.COL_MAJOR, R, c, cfg, stream)
+            if st != 0:
+                raise tsnmf.TsnmfError("tsnmf_tsqr_r", st)
+
+        heat()
+        tsnmf.tsnmf_profile_query(0)
+        tsnmf.tsnmf_profile_enable(2)
+        t = _timed(torch, heat, 5)
+        tsnmf.tsnmf_profile_enable(0)
+        _, lms, lcalls = tsnmf.tsnmf_profile_query(0)
+        tsnmf.tsnmf_profile_query(1)
+        lavg = lms / max(lcalls, 1) * 1e-3
+        out["heat_transfer"][name] = {"ms": round(t * 1e3, 3), "gbs": round(hb / t / 1e9, 1),
+                                      "leaf_ms": round(lavg * 1e3, 3), "leaf_gbs": round(hb / lavg / 1e9, 1),
+                                      "leaf_tflops": round(hflops / lavg / 1e12, 1),
+                                      "leaf_frac_fp32": round(hflops / lavg / 1e12 / FP32_VECTOR_PEAK, 4)}
     del X, d
     torch.cuda.empty_cache()
 
@@ -273,10 +305,27 @@ def extras(torch, tsnmf, synth, dev, check=True):
         proj[name] = {"ms": round(t * 1e3, 3), "tflops": round(tf, 1), "peak_tflops": peak,
                       "frac": round(tf / peak, 4), "gbs": round(Xin.numel() * Xin.element_size() / t / 1e9, 1),
                       "gnormals_per_s": round(m * k / t / 1e9, 1)}
-    # each Gaussian feeds 2 n = 256 flops, so the matrix cores need 4 normals
-    # per SIMD per clock; Philox-10 + Box-Muller on the vector units makes the
-    # generation, not the MFMA, the bound of the BF16 path
-    out["projection"] = {"workload": "20,000,000 x 128, k = 512", "gaussians": m * k, **proj}
+    # the generator alone on the matrix-core kernel's launch shape (G^T 1, no X
+    # read): the ceiling of the BF16 path, whose MFMA work is 2 n = 256 flops
+    # per normal
+    sbuf = torch.empty(k, dtype=torch.float32, device=dev)
+
+    def gen():
+        st = tsnmf.tsnmf_gauss_colsum(m, k, 14026964, 0, sbuf, stream)
+        if st != 0:
+            raise tsnmf.TsnmfError("tsnmf_gauss_colsum", st)
+    gen()
+    tsnmf.tsnmf_profile_query(0)
+    tsnmf.tsnmf_profile_enable(2)
+    t = _timed(torch, gen, 3)
+    tsnmf.tsnmf_profile_enable(0)
+    _, gms, gcalls = tsnmf.tsnmf_profile_query(0)
+    gker = gms / max(gcalls, 1) * 1e-3
+    rng = {"ms": round(t * 1e3, 3), "kernel_ms": round(gker * 1e3, 3),
+           "gnormals_per_s": round(m * k / gker / 1e9, 1)}
+    proj["bf16_mfma"]["frac_of_generator_ceiling"] = round(gker * 1e3 / proj["bf16_mfma"]["ms"], 4)
+    out["projection"] = {"workload": "20,000,000 x 128, k = 512", "gaussians": m * k, **proj,
+                         "generator_alone": rng}
     del X, Xb, d, Y
     torch.cuda.empty_cache()
 
@@ -293,8 +342,39 @@ def extras(torch, tsnmf, synth, dev, check=True):
 
     small()
     t = _timed(torch, small, 20)
-    out["plain_fp64"] = {"workload": "100,000 x 20 FP64 row-major", "ms": round(t * 1e3, 4),
-                         "gbs": round(m * n * 8 / t / 1e9, 1)}
+    # the whole example on the GPU: TSQR with 1,000-row leaves and a binary
+    # tree, SPA on R D^{-1} (r = 10), NNLS for H and the residual, stream
+    # ordered with no host synchronisation, then the same captured in a graph
+    r = d["r"]
+    cs1 = torch.empty(n, dtype=torch.float64, device=dev)
+    K = torch.empty(r, dtype=torch.int32, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    H = torch.empty((n, r), dtype=torch.float64, device=dev)
+    rel = torch.empty(1, dtype=torch.float64, device=dev)
+    cfg1 = tsnmf.TsqrConfig(leaf_rows=1000, tree_arity=2, rows_per_lane=0, wy_panel=0)
+
+    def pipeline(s=stream):
+        for st in (tsnmf.tsnmf_tsqr_r_ex(X, m, n, n, tsnmf.F64, R, cs1, cfg1, s),
+                   tsnmf.tsnmf_select_spa(R, n, n, n, cs1, r, K, None, info, s),
+                   tsnmf.tsnmf_nnls(R, n, n, n, K, r, H, r, None, None, s),
+                   tsnmf.tsnmf_residual(R, n, n, n, K, r, H, r, rel, s)):
+            if st != 0:
+                raise tsnmf.TsnmfError("pipeline", st)
+
+    pipeline()
+    tp = _timed(torch, pipeline, 20)
+    gs = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    gp_ = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gp_, stream=gs):
+        pipeline(gs.cuda_stream)
+    gp_.replay()
+    tg = _timed(torch, gp_.replay, 20)
+    out["plain_fp64"] = {"workload": "100,000 x 20 FP64 row-major", "tsqr_ms": round(t * 1e3, 4),
+                         "tsqr_gbs": round(m * n * 8 / t / 1e9, 1),
+                         "pipeline": "TSQR (1,000-row leaves, binary tree) -> SPA (r = 10) -> NNLS -> residual",
+                         "pipeline_us": round(tp * 1e6, 1), "pipeline_graph_us": round(tg * 1e6, 1),
+                         "K": sorted(K.cpu().tolist()), "K_planted": d["K"], "residual": float(rel.item())}
     return out
 
 
@@ -316,6 +396,13 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    # the committed autotune table: tsnmf_tsqr_r applies its matching entries
+    tuned = None
+    if os.path.exists(TUNED_FILE):
+        if tsnmf.tsnmf_tune_load(TUNED_FILE) != 0:
+            raise RuntimeError(f"cannot load {TUNED_FILE}")
+        from paper_1402_6964_amd import tune as _tune
+        tuned = _tune.load(TUNED_FILE)
     if args.copy_reference:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -369,7 +456,7 @@ def main():
     gbs = wl["bytes"] / (ms_per_step * 1e-3) / 1e9
     leaf_avg_ms = leaf_ms / max(leaf_calls, 1)
     achieved = wl["bytes"] / (leaf_avg_ms * 1e-3) / 1e9
-    leaf_flops = 2 * wl["m"] * wl["n"] * (wl["n"] + 1)
+    leaf_flops = 2 * wl["m"] * wl["n"] * wl["n"]          # 2 m n^2, the Householder work of the leaves
     leaf_tflops = leaf_flops / (leaf_avg_ms * 1e-3) / 1e12
     traffic = read_traffic()
     line = {
@@ -386,19 +473,23 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {**wl, "workload": "flow_cytometry 10,000,000 x 25 FP32 row-major (1.0 GB), "
-                                     "FP32 Householder leaves + FP64 tree"},
+                                     "FP32 Householder leaves + FP64 tree",
+                   "geometry": geometry(tuned, "f32", "row", "f32", 1, wl["n"], wl["m"])},
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-        # The leaf kernel does 2 m n (n + 1) FP32 flops on 4 m n bytes (13 flop/B
-        # at n = 25), above the 9.8 flop/B ridge of FP32 FMA without packed
-        # instructions (78.6 TF/s: 256 CUs x 64 lanes x 2 flops x 2.4 GHz), so
-        # the ALU bounds it; the HBM view is reported beside it.
-        "roofline": {"bound": "alu", "achieved": round(leaf_tflops, 2), "peak": ALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(leaf_tflops / ALU_PEAK_TFLOPS, 4), "traffic": traffic,
+        # The leaf kernel reads 4 m n bytes and does 2 m n^2 FP32 flops: 12.5
+        # flop/B, below the 19.7 flop/B ridge of the 157.3 TF/s FP32 peak, so
+        # its roof is HBM.  The ALU view rides along: against 157.3 TF/s, and
+        # against 78.6 TF/s, the FP32 FMA rate of the vector ALUs without the
+        # packed instructions this build does not emit.
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": LEAF_KERNEL, "kernel_avg_ms": round(leaf_avg_ms, 5),
-                     "algorithmic_flops_per_launch": leaf_flops,
                      "algorithmic_bytes_per_launch": wl["bytes"],
-                     "hbm": {"achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(achieved / HBM_PEAK_GBS, 4)}},
+                     "algorithmic_flops_per_launch": leaf_flops,
+                     "alu": {"achieved": round(leaf_tflops, 2), "unit": "TFLOP/s",
+                             "peak_fp32": FP32_VECTOR_PEAK, "frac_fp32": round(leaf_tflops / FP32_VECTOR_PEAK, 4),
+                             "peak_fp32_unpacked": FP32_UNPACKED_PEAK,
+                             "frac_fp32_unpacked": round(leaf_tflops / FP32_UNPACKED_PEAK, 4)}},
         "tail_avg_ms": round(tail_ms / max(tail_calls, 1), 5),
     }
     _note(f"main: {ms_per_step:.4f} ms per step")
@@ -409,7 +500,7 @@ def main():
     if not args.no_extras:
         del X, d
         torch.cuda.empty_cache()
-        line["extras"] = extras(torch, tsnmf, synth, dev, check=not args.no_cpu)
+        line["extras"] = extras(torch, tsnmf, synth, dev, check=not args.no_cpu, tuned=tuned)
     print(json.dumps(line), flush=True)
 
 

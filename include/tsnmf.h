@@ -134,6 +134,16 @@ typedef struct tsnmf_tsqr_config {
                                Other values: -8 from tsnmf_tsqr_r_ex.        */
     int32_t rows_per_lane;  /* reserved, must be 0: the row block height is fixed
                                per width when the library is compiled        */
+    int32_t wy_panel;       /* trailing update of FP32 row blocks with 33..64
+                               columns (Sec. 3.1: any grouping of the
+                               Householder steps gives the same R): 16 =
+                               blocked compact-WY update on the matrix cores
+                               with 16-column panels; 0 (library default) or
+                               1 = unblocked (each step updates every trailing
+                               column on the vector ALUs).  Other widths and
+                               FP64 row blocks are unblocked.  Other values:
+                               -8.                                            */
+    int32_t reserved;       /* must be 0                                      */
 } tsnmf_tsqr_config;
 
 /* As tsnmf_tsqr_r with an explicit configuration (`cfg` is a host pointer or
@@ -142,6 +152,26 @@ typedef struct tsnmf_tsqr_config {
 int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t flags,
                     double* R, double* colsum, const tsnmf_tsqr_config* cfg,
                     hipStream_t stream);
+
+/*
+ * tsnmf_tsqr_r_kron: tsnmf_tsqr_r of X = A (x) A without X in memory.  The
+ * flow-cytometry matrix of Sec. 5.2 is this Kronecker product of a p x 5
+ * matrix of cell measurements with itself (all pairs of cells); here each
+ * row block of X is formed in registers from the rows of A it needs, so only
+ * A (p x q, a few MB) is read, and X (p^2 x q^2) never exists.
+ *   A       device FP32, p x q, row-major (lda >= q); row i p + i' of X holds
+ *           A(i, a) A(i', b) in column a q + b, each product rounded to FP32
+ *           once (the bytes an explicit FP32 X would hold).
+ *   p       1 <= p <= 2^31;  q  1..5 (n = q^2 <= 25)
+ *   R       device FP64 n x n column-major output (diag >= 0, R^T R = X^T X;
+ *           in exact arithmetic R = R_A (x) R_A)
+ *   colsum  device FP64[n] or NULL: l1 column sums of X
+ * Same row blocks, slabs and tree as tsnmf_tsqr_r on the explicit X with
+ * ld = n and the library default, so both give the same R.
+ * Errors: -1 A NULL, -2 p, -3 q, -4 lda < q, -5 R NULL.
+ */
+int tsnmf_tsqr_r_kron(const float* A, int64_t p, int32_t q, int64_t lda, double* R, double* colsum,
+                      hipStream_t stream);
 
 /* ---- batched thin QR ---------------------------------------------------------- */
 
@@ -215,6 +245,21 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
                      int32_t k, uint64_t seed, int64_t row_offset, float* Y,
                      double* colsum, hipStream_t stream);
 
+/*
+ * tsnmf_gauss_colsum: s = G^T 1, i.e. s[l] = sum_{i < m} G(row_offset + i, l)
+ * for the G of tsnmf_gauss_proj (the projection of a column of ones), computed
+ * without reading any X.  It draws the normals exactly as the matrix-core
+ * projection does (same launch shape and generation loop), so its time is the
+ * cost of generating G alone; s also checks the generator's first moment
+ * (E s[l] = 0, Var s[l] = m).
+ *   m           rows of G (>= 1);  k  multiple of 4, 4 <= k <= 4096
+ *   seed, row_offset  as in tsnmf_gauss_proj
+ *   s           device FP32[k] output (FP32 sums per lane, FP64 across workgroups)
+ * Errors: -1 m, -2 k, -4 row_offset < 0, -5 s NULL.
+ */
+int tsnmf_gauss_colsum(int64_t m, int32_t k, uint64_t seed, int64_t row_offset, float* s,
+                       hipStream_t stream);
+
 /* ---- n x n steps (FP64, one workgroup each) --------------------------------------- */
 
 /*
@@ -283,6 +328,47 @@ int tsnmf_nnls(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t
  */
 int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int32_t* K,
                    int32_t r, const double* H, int32_t ldh, double* relerr, hipStream_t stream);
+
+/*
+ * tsnmf_rsvd: SVD of the n x n factor R = U diag(S) V^T (Sec. 3.1, "TSQR and
+ * R-SVD": with X = QR, X = (QU) diag(S) V^T, so S and V are the singular
+ * values and right singular vectors of X).  FP64 one-sided Jacobi on one
+ * workgroup, which determines small singular values to high relative
+ * accuracy.
+ *   R     device FP64 n x n column-major (ldr >= n), 1 <= n <= 256
+ *   S     device FP64[n] output, descending
+ *   V     device FP64 n x n column-major output (ldv >= n)
+ *   U     device FP64 n x n column-major output (ldu >= n) or NULL; columns of
+ *         zero singular values are zero
+ *   info  device int32[1] or NULL: Jacobi sweeps used, -1 if not converged in 40
+ * Each pair (u_i, v_i) is signed so that the largest-magnitude entry of v_i
+ * is positive.  Errors: -1 R, -2 n, -3 ldr, -4 S, -5 V, -6 ldv, -8 ldu.
+ */
+int tsnmf_rsvd(const double* R, int32_t n, int32_t ldr, double* S, double* V, int32_t ldv, double* U,
+               int32_t ldu, int32_t* info, hipStream_t stream);
+
+/*
+ * tsnmf_rank_sweep: residuals of the separable fit for every rank 1..rmax in
+ * the reduced space (Sec. 2.2, Sec. 2.4: the selection, the NNLS fit and the
+ * residual are the same on R as on X, so a whole residual curve costs n x n
+ * work).  K = SPA's rmax picks on R diag(1/colscale) (in order; the first r
+ * are SPA's picks for r); for each r, H_r = NNLS(R(:, K[:r]), R) and
+ * resid[r-1] = ||R - R(:, K[:r]) H_r||_F^2 / ||R||_F^2.
+ *   R, p, n, ldr  device FP64 p x n column-major, p, n in 1..256
+ *   colscale      device FP64[n] or NULL (as tsnmf_select_spa)
+ *   rmax          1..min(n, 64)
+ *   K             device int32[rmax] output
+ *   H             device FP64 rmax x n (ldh >= rmax): work space; on return
+ *                 H_rmax in its first rmax rows
+ *   resid         device FP64[rmax] output
+ *   info          device int32[1] output: SPA's picks (< rmax if the residual
+ *                 reached 0 first; resid is NaN past it)
+ * Errors: -1 R, -2 p, -3 n, -4 ldr, -6 rmax, -7 K, -8 H, -9 ldh, -10 resid,
+ * -11 info.
+ */
+int tsnmf_rank_sweep(const double* R, int32_t p, int32_t n, int32_t ldr, const double* colscale,
+                     int32_t rmax, int32_t* K, double* H, int32_t ldh, double* resid, int32_t* info,
+                     hipStream_t stream);
 
 /* ---- housekeeping ------------------------------------------------------------------- */
 

@@ -164,7 +164,8 @@ int tsnmf_tsqr_r_ex(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t fl
     if (R == nullptr) return -6;
     if (cfg != nullptr) {
         if (cfg->leaf_rows < 0 || (cfg->tree_arity != 0 && (cfg->tree_arity < 2 || cfg->tree_arity > 64)) ||
-            cfg->rows_per_lane != 0)
+            cfg->rows_per_lane != 0 || (cfg->wy_panel != 0 && cfg->wy_panel != 1 && cfg->wy_panel != 16) ||
+            cfg->reserved != 0)
             return -8;
     }
     if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
@@ -192,6 +193,16 @@ int tsnmf_tsqr_r_noalloc(const void* X, int64_t m, int64_t n, int64_t ld, uint32
     if (R == nullptr) return -6;
     if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
     return tsqr_r_noalloc_impl(X, m, (int)n, ld, flags, R, colsum, stream);
+}
+
+int tsnmf_tsqr_r_kron(const float* A, int64_t p, int32_t q, int64_t lda, double* R, double* colsum,
+                      hipStream_t stream) {
+    if (A == nullptr) return -1;
+    if (p < 1 || p > ((int64_t)1 << 31)) return -2;
+    if (q < 1 || q > 5) return -3;
+    if (lda < q) return -4;
+    if (R == nullptr) return -5;
+    return tsqr_r_kron_impl(A, p, q, lda, R, colsum, stream);
 }
 
 int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
@@ -230,6 +241,14 @@ int tsnmf_gauss_proj(const void* X, int64_t m, int64_t n, int64_t ld, uint32_t f
     if (Y == nullptr) return -9;
     if (n > TSNMF_MAX_N) return TSNMF_ERR_UNSUPPORTED;
     return gauss_proj_impl(X, m, (int)n, ld, flags, k, seed, row_offset, Y, colsum, stream);
+}
+
+int tsnmf_gauss_colsum(int64_t m, int32_t k, uint64_t seed, int64_t row_offset, float* s, hipStream_t stream) {
+    if (m < 1) return -1;
+    if (k < 4 || k > 4096 || (k % 4) != 0) return -2;
+    if (row_offset < 0) return -4;
+    if (s == nullptr) return -5;
+    return gauss_colsum_impl(m, k, seed, row_offset, s, stream);
 }
 
 static const int kMaxSmall = 256;   // p, n bound of the n x n solvers
@@ -297,6 +316,33 @@ int tsnmf_residual(const double* M, int32_t p, int32_t n, int32_t ldm, const int
     if (ldh < r) return -8;
     if (relerr == nullptr) return -9;
     return residual_impl(M, p, n, ldm, K, r, H, ldh, relerr, stream);
+}
+
+int tsnmf_rsvd(const double* R, int32_t n, int32_t ldr, double* S, double* V, int32_t ldv, double* U, int32_t ldu,
+               int32_t* info, hipStream_t stream) {
+    if (R == nullptr) return -1;
+    if (n < 1 || n > kMaxSmall) return -2;
+    if (ldr < n) return -3;
+    if (S == nullptr) return -4;
+    if (V == nullptr) return -5;
+    if (ldv < n) return -6;
+    if (U != nullptr && ldu < n) return -8;
+    return rsvd_impl(R, n, ldr, S, V, ldv, U, ldu, info, stream);
+}
+
+int tsnmf_rank_sweep(const double* R, int32_t p, int32_t n, int32_t ldr, const double* colscale, int32_t rmax,
+                     int32_t* K, double* H, int32_t ldh, double* resid, int32_t* info, hipStream_t stream) {
+    if (R == nullptr) return -1;
+    if (p < 1 || p > kMaxSmall) return -2;
+    if (n < 1 || n > kMaxSmall) return -3;
+    if (ldr < p) return -4;
+    if (rmax < 1 || rmax > n || rmax > kMaxPicks) return -6;
+    if (K == nullptr) return -7;
+    if (H == nullptr) return -8;
+    if (ldh < rmax) return -9;
+    if (resid == nullptr) return -10;
+    if (info == nullptr) return -11;
+    return rank_sweep_impl(R, p, n, ldr, colscale, rmax, K, H, ldh, resid, info, stream);
 }
 
 int tsnmf_reserve(int64_t max_m, int32_t max_n, int32_t max_k) {

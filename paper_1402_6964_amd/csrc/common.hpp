@@ -65,6 +65,12 @@ int residual_impl(const double* M, int p, int n, int ldm, const int* K, int r, c
                   double* relerr, hipStream_t stream);
 int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
                     int64_t row_offset, float* Y, double* colsum, hipStream_t stream);
+int tsqr_r_kron_impl(const float* A, int64_t p, int q, int64_t lda, double* R, double* colsum, hipStream_t stream);
+int rsvd_impl(const double* R, int n, int ldr, double* S, double* V, int ldv, double* U, int ldu, int* info,
+              hipStream_t stream);
+int rank_sweep_impl(const double* R, int p, int n, int ldr, const double* colscale, int rmax, int* K, double* H,
+                    int ldh, double* resid, int* info, hipStream_t stream);
+int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float* out, hipStream_t stream);
 int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const int64_t* n, const int64_t* ld,
                       double* const* R, double* const* colsum, hipStream_t stream);
 int batch_reserve(int32_t max_batch, int64_t max_rows);

@@ -259,6 +259,46 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
     }
 }
 
+// ---- the generator alone: G^T 1 ------------------------------------------------------
+//
+// The projection of a column of ones, with nothing read from memory: the same
+// launch shape and generation loop as gp_mfma_kernel (row ranges x 512-wide
+// column ranges, 8 waves x 16 column groups, 32-row chunks in which lane L
+// draws the Philox blocks of rows 8 (L / 16) .. 8 (L / 16) + 7 of group
+// L % 16), so its time is the cost of drawing the normals of that kernel.
+// Each lane sums its normals in FP32, the four lanes of a group are added,
+// and the workgroup partials are summed in FP64 by gp_reduce_kernel (n = 1).
+__global__ void __launch_bounds__(512) gp_colsum_kernel(GpArgs a) {
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, L = tid & 63;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
+    const int lbase = blockIdx.y * 512 + wv * 64;
+    const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t i = i0 + 8 * (L >> 4) + t;
+            float g[4];
+            gauss4(a.row_offset + i, q, a.key0, a.key1, g);
+            const bool in = i < r1;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[s] += in ? g[s] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = allreduce_stage<4>(allreduce_stage<5>(acc[s]));
+    if (L < 16) {
+        float* P = a.part + (int64_t)blockIdx.x * a.k;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int l = 4 * (int)q + s;
+            if (l < a.k) P[l] = acc[s];
+        }
+    }
+}
+
 // Sum of the workgroup partials in FP64, in workgroup order; Y column-major.
 __global__ void gp_reduce_kernel(const float* __restrict__ part, int64_t nparts, int k, int n, float* __restrict__ Y,
                                  const double* __restrict__ part_cs, double* __restrict__ colsum) {
@@ -284,6 +324,36 @@ int64_t gp_rows_per_wg(int64_t m, int rows_multiple) {
 }
 
 }  // namespace
+
+int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float* out, hipStream_t stream) {
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    const int64_t parts = (m + rpw - 1) / rpw;
+    void* ws = nullptr;
+    if (int st = workspace_get(kTicketBytes + (size_t)parts * k * 4 + 256, stream, &ws)) return st;
+    GpArgs a{};
+    a.m = m;
+    a.n = 1;
+    a.k = k;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.row_offset = row_offset;
+    a.rows_per_wg = rpw;
+    a.part = (float*)((char*)ws + kTicketBytes);
+    const bool prof = profiling_on();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof)
+        if (int st = profile_event(stream, &e0)) return st;
+    hipLaunchKernelGGL(gp_colsum_kernel, dim3((unsigned)parts, (unsigned)((k + 511) / 512)), dim3(512), 0, stream, a);
+    TSNMF_LAUNCH_CHECK();
+    if (prof) {
+        if (int st = profile_event(stream, &e1)) return st;
+        profile_record(0, e0, e1);
+    }
+    hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, a.part, parts, k, 1,
+                       out, nullptr, nullptr);
+    TSNMF_LAUNCH_CHECK();
+    return TSNMF_OK;
+}
 
 size_t gp_workspace_bytes(int64_t m, int n, int k) {
     const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);

@@ -35,6 +35,10 @@ hipError_t launch_xl_f64_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_xl_f32w_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_xl_f32w_col(const WideArgs& a, hipStream_t s);
 size_t xl_rslot_bytes();
+hipError_t launch_wy_f32_col(const WideArgs& a, hipStream_t s);
+hipError_t launch_wy_f32_row(const WideArgs& a, hipStream_t s);
+int wy_block_rows();
+hipError_t launch_small_kron(int q, const StreamArgs& a, hipStream_t s);
 
 namespace {
 
@@ -82,6 +86,7 @@ hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
 struct Plan {
     Path path;
     bool wide;
+    bool wy;         // blocked compact-WY leaf (FP32 blocks, 33..64 columns)
     int waves;       // waves per slab
     int load;
     int64_t block_rows;
@@ -114,7 +119,16 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     if (p.wide && n <= 128 && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
     // above 128 columns: 8 waves x 32 columns, FP32 4 rows per lane, FP64 2
-    const int rpl = n > 128 ? (f32 ? 4 : 2)
+    // FP32 blocks of 33..64 columns: the blocked compact-WY leaf (8 waves,
+    // 512-row blocks) when the configuration asks for it; the unblocked leaf
+    // is the default (5e7 x 64 column-major: 11.5 ms against 20.9 ms)
+    p.wy = f32 && n >= 33 && n <= 64 && cfg != nullptr && cfg->wy_panel == 16;
+    if (p.wy) {
+        p.waves = 8;
+        p.load = col ? LOAD_COL : LOAD_ROW;
+    }
+    const int rpl = p.wy ? wy_block_rows() / 64
+                    : n > 128 ? (f32 ? 4 : 2)
                     : p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
                                 : f32 ? (f32_8x8 ? 22 : (n <= 64 && !col ? 12 : 11)) : 4)
                              : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
@@ -271,7 +285,9 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
     if (prof) {
         if (int st = profile_event(stream, &e0)) return st;
     }
-    if (p.wide) {
+    if (p.wy) {
+        TSNMF_HIP(p.load == LOAD_COL ? launch_wy_f32_col(aw, stream) : launch_wy_f32_row(aw, stream));
+    } else if (p.wide) {
         TSNMF_HIP(launch_wide(p.path, p.load, aw, stream));
     } else {
         TSNMF_HIP(launch_leaf(p.path, p.load, n, a, stream));
@@ -287,6 +303,50 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
         } else {
             if (int st = profile_event(stream, &e1)) return st;
             profile_record(0, e0, e1);
+        }
+    }
+    return TSNMF_OK;
+}
+
+// X = A (x) A (p^2 x q^2) formed in the leaf from A (Sec. 5.2), with the plan
+// of an explicit contiguous FP32 X of that shape.
+int tsqr_r_kron_impl(const float* A, int64_t p, int q, int64_t lda, double* R, double* colsum, hipStream_t stream) {
+    const int n = q * q;
+    const int64_t m = p * p;
+    Plan pl = make_plan(m, n, n, TSNMF_F32, nullptr);
+    if (pl.wide || pl.load != LOAD_ROW_STAGED) return TSNMF_ERR_UNSUPPORTED;   // not reached for q <= 5
+    void* ws = nullptr;
+    if (int st = workspace_get(plan_bytes(pl, n), stream, &ws)) return st;
+    const int64_t nodes = tree_nodes(pl.streams);
+    char* base = (char*)ws;
+    TreeArgs tree{};
+    tree.tickets = (int*)base;
+    tree.nodes = (double*)(base + kTicketBytes);
+    tree.node_cs = (double*)(base + kTicketBytes + align256(nodes * (size_t)n * n * 8));
+    tree.leaves = pl.streams;
+    tree.R = R;
+    tree.colsum = colsum;
+    StreamArgs a{};
+    a.X = A;
+    a.m = m;
+    a.ld = lda;
+    a.slab = pl.slab;
+    a.nstreams = pl.streams;
+    a.tree = tree;
+    a.kp = p;
+    const bool prof = profiling_on();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof)
+        if (int st = profile_event(stream, &e0)) return st;
+    TSNMF_HIP(launch_small_kron(q, a, stream));
+    if (prof) {
+        hipEvent_t m0 = nullptr, m1 = nullptr;
+        if (profile_take_split(&m0, &m1)) {
+            profile_record(0, e0, m0);
+            if (m1 != nullptr) {
+                if (int st = profile_event(stream, &e1)) return st;
+                profile_record(1, m1, e1);
+            }
         }
     }
     return TSNMF_OK;

@@ -25,7 +25,11 @@
 
 namespace tsnmf {
 
-enum LoadKind : int { LOAD_ROW = 0, LOAD_ROW_STAGED = 1, LOAD_COL = 2 };
+// LOAD_KRON: no X in memory; row i p + i' of X = A (x) A is formed from rows
+// i and i' of the small factor A (p x q, row-major, ld) as the products
+// A(i, a) A(i', b) in column a q + b (the construction of the flow-cytometry
+// matrix in Sec. 5.2).
+enum LoadKind : int { LOAD_ROW = 0, LOAD_ROW_STAGED = 1, LOAD_COL = 2, LOAD_KRON = 4 };
 // Largest slab (bytes) of the FP32 staged path, which addresses a slab
 // through one buffer resource with a 32-bit byte range.
 constexpr int64_t kMaxBufSlabBytes = ((int64_t)1 << 31) - 4096;
@@ -37,6 +41,7 @@ struct StreamArgs {
     int64_t slab;          // rows per stream
     int64_t nstreams;      // streams (one wave each) = tree leaves
     TreeArgs tree;         // reduction tree and final outputs
+    int64_t kp;            // LOAD_KRON: rows p of the factor A (X has p^2 rows)
 };
 
 // 1 / x: the hardware estimate in FP32; in FP64 the estimate refined by two
@@ -278,6 +283,30 @@ template <typename T, typename TI, int N, int RPL> struct Small {
 #pragma unroll
                 for (int c = 0; c < N; ++c) x[r][c] = (T)St[L * SS + c];
                 wave_lds_sync();
+            }
+        } else if constexpr (LOAD == LOAD_KRON) {
+            // X = A (x) A with A p x Q row-major (ld): one FP32 product per
+            // element, as an explicit X would hold it
+            constexpr int Q = N == 1 ? 1 : N == 4 ? 2 : N == 9 ? 3 : N == 16 ? 4 : 5;
+            static_assert(Q * Q == N, "LOAD_KRON widths are squares up to 25");
+            const float* A = (const float*)a.X;
+            const uint64_t p = (uint64_t)a.kp;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t i = b0 + r * 64 + L;
+                const bool ok = i < r1;
+                const uint64_t ii = (uint64_t)min(i, a.m - 1);
+                const uint64_t ia = ii / p, ib = ii - ia * p;
+                float fa[Q], fb[Q];
+#pragma unroll
+                for (int c = 0; c < Q; ++c) {
+                    fa[c] = A[ia * a.ld + c];
+                    fb[c] = A[ib * a.ld + c];
+                }
+#pragma unroll
+                for (int ca = 0; ca < Q; ++ca)
+#pragma unroll
+                    for (int cb = 0; cb < Q; ++cb) x[r][ca * Q + cb] = ok ? (T)(fa[ca] * fb[cb]) : T(0);
             }
         } else if constexpr (LOAD == LOAD_COL) {
 #pragma unroll

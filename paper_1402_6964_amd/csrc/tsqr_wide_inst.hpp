@@ -14,6 +14,23 @@ namespace tsnmf {
 // cost (reflector scalars, pivot exchange, barrier) over.
 template <typename T> constexpr int wide_rpl() { return sizeof(T) == 4 ? 11 : 5; }
 
+// FP64 tree over the slab factors of `a`: groups of 4 stacked factors, each
+// factored by the wide kernel in FP64 (NW x W columns).
+template <int NW, int W, int RPLD, bool RG = false>
+hipError_t launch_wide_tree(const WideArgs& a, hipStream_t stream) {
+    constexpr int G = 4;
+    using M = Wide<double, double, NW, W, RPLD, RG>;
+    const size_t mlds = M::lds_bytes();
+    auto mk = tsqr_wide_merge_kernel<NW, W, RPLD, G, RG>;
+    if (mlds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)mk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t groups = (a.tree.leaves + G - 1) / G;
+    hipLaunchKernelGGL(mk, dim3((unsigned)groups), dim3(W * 64), mlds, stream, a.tree, a.n);
+    return hipGetLastError();
+}
+
 template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_rpl<T>(), bool RG = false,
           int RPLD = 4>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
@@ -28,18 +45,7 @@ hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     profile_split(stream);
-    // FP64 tree: groups of 4 stacked factors, each factored by the wide kernel
-    constexpr int G = 4;
-    using M = Wide<double, double, NW, W, RPLD, RG>;
-    const size_t mlds = M::lds_bytes();
-    auto mk = tsqr_wide_merge_kernel<NW, W, RPLD, G, RG>;
-    if (mlds > 65536) {
-        e = hipFuncSetAttribute((const void*)mk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
-        if (e != hipSuccess) return e;
-    }
-    const int64_t groups = (a.tree.leaves + G - 1) / G;
-    hipLaunchKernelGGL(mk, dim3((unsigned)groups), dim3(W * 64), mlds, stream, a.tree, a.n);
-    return hipGetLastError();
+    return launch_wide_tree<NW, W, RPLD, RG>(a, stream);
 }
 
 // 129..256 columns: 8 waves x 32 columns, R of each workgroup in a global

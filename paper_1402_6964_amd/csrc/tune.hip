@@ -3,7 +3,7 @@
 // tsnmf_tune_load reads a text table written by the autotuner
 // (paper_1402_6964_amd/tune.py); tsnmf_tsqr_r then applies the entry that
 // matches each call.  A line
-//     tsqr <f32|f64> <row|col> <leaf f32|f64> <ld == n: 1|0> <n> <floor(log2 m)> <leaf_rows> <tree_arity>
+//     tsqr <f32|f64> <row|col> <leaf f32|f64> <ld == n: 1|0> <n> <floor(log2 m)> <leaf_rows> <tree_arity> [<wy_panel>]
 // keys an entry by input dtype, layout, row-block precision, whether rows are
 // contiguous, width and row-count bucket; '#' starts a comment.  Every entry
 // changes only the launch geometry, so the result equals the default's up to
@@ -71,15 +71,15 @@ extern "C" int tsnmf_tune_load(const char* path) {
         char* hash = std::strchr(line, '#');
         if (hash != nullptr) *hash = '\0';
         char kind[16], dt[8], lay[8], leaf[8];
-        int ldeq = 0, n = 0, lg = 0, arity = 0;
+        int ldeq = 0, n = 0, lg = 0, arity = 0, wy = 0;
         long long leaf_rows = 0;
-        const int got = std::sscanf(line, "%15s %7s %7s %7s %d %d %d %lld %d", kind, dt, lay, leaf, &ldeq, &n, &lg,
-                                    &leaf_rows, &arity);
+        const int got = std::sscanf(line, "%15s %7s %7s %7s %d %d %d %lld %d %d", kind, dt, lay, leaf, &ldeq, &n, &lg,
+                                    &leaf_rows, &arity, &wy);
         if (got <= 0) continue;                          // blank or comment line
         const bool f32 = !std::strcmp(dt, "f32"), f64 = !std::strcmp(dt, "f64");
         const bool row = !std::strcmp(lay, "row"), col = !std::strcmp(lay, "col");
         const bool l32 = !std::strcmp(leaf, "f32"), l64 = !std::strcmp(leaf, "f64");
-        if (got != 9 || std::strcmp(kind, "tsqr") != 0 || !(f32 || f64) || !(row || col) || !(l32 || l64) ||
+        if ((got != 9 && got != 10) || (wy != 0 && wy != 1 && wy != 16) || std::strcmp(kind, "tsqr") != 0 || !(f32 || f64) || !(row || col) || !(l32 || l64) ||
             (f64 && l32) || (ldeq != 0 && ldeq != 1) || n < 1 || n > TSNMF_MAX_N || lg < 0 || lg > 62 ||
             leaf_rows < 0 || (arity != 0 && (arity < 2 || arity > 64))) {
             ok = false;
@@ -89,6 +89,8 @@ extern "C" int tsnmf_tune_load(const char* path) {
         c.leaf_rows = leaf_rows;
         c.tree_arity = arity;
         c.rows_per_lane = 0;
+        c.wy_panel = wy;
+        c.reserved = 0;
         table[Key{f64 ? 64 : 32, col ? 1 : 0, l64 ? 1 : 0, ldeq, n, lg}] = c;
     }
     std::fclose(f);

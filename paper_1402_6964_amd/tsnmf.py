@@ -41,7 +41,8 @@ _u64 = ctypes.c_uint64
 
 
 class TsqrConfig(ctypes.Structure):
-    _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32)]
+    _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32), ("wy_panel", _i32),
+                ("reserved", _i32)]
 
 
 class _Entry:
@@ -68,15 +69,20 @@ _tsqr_r = _sig("tsnmf_tsqr_r", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, 
 _tsqr_r_noalloc = _sig("tsnmf_tsqr_r_noalloc", ctypes.c_int, [_vp, _i64, _i64, _i64, _u32, _vp, _vp, _vp])
 _tsqr_r_ex = _sig("tsnmf_tsqr_r_ex", ctypes.c_int,
                   [_vp, _i64, _i64, _i64, _u32, _vp, _vp, ctypes.POINTER(TsqrConfig), _vp])
+_tsqr_r_kron = _sig("tsnmf_tsqr_r_kron", ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _vp, _vp])
 _tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp])
 _reserve_batched = _sig("tsnmf_reserve_batched", ctypes.c_int, [_i32, _i64])
 _gauss_proj = _sig("tsnmf_gauss_proj", ctypes.c_int,
                    [_vp, _i64, _i64, _i64, _u32, _i32, _u64, _i64, _vp, _vp, _vp])
+_gauss_colsum = _sig("tsnmf_gauss_colsum", ctypes.c_int, [_i64, _i32, _u64, _i64, _vp, _vp])
 _select_spa = _sig("tsnmf_select_spa", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp])
 _select_xray = _sig("tsnmf_select_xray", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp])
 _select_gp = _sig("tsnmf_select_gp", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp])
 _nnls = _sig("tsnmf_nnls", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp])
 _residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp])
+_rsvd = _sig("tsnmf_rsvd", ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp])
+_rank_sweep = _sig("tsnmf_rank_sweep", ctypes.c_int,
+                   [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp])
 _reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
 _workspace_release = _sig("tsnmf_workspace_release", ctypes.c_int, [])
 _tune_load = _sig("tsnmf_tune_load", ctypes.c_int, [ctypes.c_char_p])
@@ -134,6 +140,10 @@ def tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):
     return _tsqr_r_ex(_ptr(X), m, n, ld, flags, _ptr(R), _ptr(colsum), c, _stream(stream))
 
 
+def tsnmf_tsqr_r_kron(A, p, q, lda, R, colsum=None, stream=None):
+    return _tsqr_r_kron(_ptr(A), p, q, lda, _ptr(R), _ptr(colsum), _stream(stream))
+
+
 def tsnmf_tsqr_r_batched(batch, X, m, n, ld, flags, R, colsum=None, stream=None):
     return _tsqr_batched(batch, _ptr(X), _ptr(m), _ptr(n), _ptr(ld), flags, _ptr(R), _ptr(colsum),
                          _stream(stream))
@@ -145,6 +155,10 @@ def tsnmf_reserve_batched(max_batch, max_rows):
 
 def tsnmf_gauss_proj(X, m, n, ld, flags, k, seed, row_offset, Y, colsum=None, stream=None):
     return _gauss_proj(_ptr(X), m, n, ld, flags, k, seed, row_offset, _ptr(Y), _ptr(colsum), _stream(stream))
+
+
+def tsnmf_gauss_colsum(m, k, seed, row_offset, s, stream=None):
+    return _gauss_colsum(m, k, seed, row_offset, _ptr(s), _stream(stream))
 
 
 def tsnmf_select_spa(M, p, n, ldm, colscale, r, K, score, info, stream=None):
@@ -165,6 +179,15 @@ def tsnmf_nnls(M, p, n, ldm, K, r, H, ldh, resid2=None, info=None, stream=None):
 
 def tsnmf_residual(M, p, n, ldm, K, r, H, ldh, relerr, stream=None):
     return _residual(_ptr(M), p, n, ldm, _ptr(K), r, _ptr(H), ldh, _ptr(relerr), _stream(stream))
+
+
+def tsnmf_rsvd(R, n, ldr, S, V, ldv, U=None, ldu=0, info=None, stream=None):
+    return _rsvd(_ptr(R), n, ldr, _ptr(S), _ptr(V), ldv, _ptr(U), ldu, _ptr(info), _stream(stream))
+
+
+def tsnmf_rank_sweep(R, p, n, ldr, colscale, rmax, K, H, ldh, resid, info, stream=None):
+    return _rank_sweep(_ptr(R), p, n, ldr, _ptr(colscale), rmax, _ptr(K), _ptr(H), ldh, _ptr(resid), _ptr(info),
+                       _stream(stream))
 
 
 def tsnmf_reserve(max_m, max_n, max_k=0):
@@ -249,6 +272,20 @@ def tsqr_r(X, leaf_f64=False, config=None, stream=None, with_colsum=True):
     return colmajor_square(Rbuf), cs
 
 
+def tsqr_r_kron(A, stream=None, with_colsum=True):
+    """R and column sums of X = A (x) A for a row-major FP32 CUDA tensor A
+    (p x q, q <= 5), without forming X."""
+    p, q = A.shape
+    lay, lda = _layout(A)
+    if lay != ROW_MAJOR or A.dtype != torch.float32:
+        raise ValueError("A must be a row-major float32 tensor")
+    n = q * q
+    Rbuf = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    cs = torch.empty(n, dtype=torch.float64, device=A.device) if with_colsum else None
+    _check("tsnmf_tsqr_r_kron", tsnmf_tsqr_r_kron(A, p, q, lda, Rbuf, cs, stream))
+    return colmajor_square(Rbuf), cs
+
+
 def gauss_proj(X, k, seed, mode=None, row_offset=0, stream=None, with_colsum=False):
     """Y = G^T X (k x n, FP32) with the library's Philox-defined G."""
     m, n = X.shape
@@ -262,6 +299,13 @@ def gauss_proj(X, k, seed, mode=None, row_offset=0, stream=None, with_colsum=Fal
     cs = torch.empty(n, dtype=torch.float64, device=X.device) if with_colsum else None
     _check("tsnmf_gauss_proj", tsnmf_gauss_proj(X, m, n, ld, flags, k, seed, row_offset, Ybuf, cs, stream))
     return Ybuf.t(), cs
+
+
+def gauss_colsum(m, k, seed, row_offset=0, device="cuda", stream=None):
+    """G^T 1 (k values) for the projection's G, without reading any X."""
+    out = torch.empty(k, dtype=torch.float32, device=device)
+    _check("tsnmf_gauss_colsum", tsnmf_gauss_colsum(m, k, seed, row_offset, out, stream))
+    return out
 
 
 def _colmajor_input(M):
@@ -320,6 +364,32 @@ def residual(M, K, H, stream=None):
     out = torch.empty(1, dtype=torch.float64, device=M.device)
     _check("tsnmf_residual", tsnmf_residual(Mc, p, n, ldm, K, r, Hc, ldh, out, stream))
     return out
+
+
+def rsvd(R, with_u=True, stream=None):
+    """(S, U, V) of an n x n FP64 CUDA matrix R (R = U diag(S) V^T), and the
+    number of Jacobi sweeps."""
+    n = R.shape[0]
+    Rc, ldr = _colmajor_input(R)
+    S = torch.empty(n, dtype=torch.float64, device=R.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    Ub = torch.empty((n, n), dtype=torch.float64, device=R.device) if with_u else None
+    info = torch.empty(1, dtype=torch.int32, device=R.device)
+    _check("tsnmf_rsvd", tsnmf_rsvd(Rc, n, ldr, S, Vb, n, Ub, n if with_u else 0, info, stream))
+    return S, (Ub.t() if with_u else None), Vb.t(), info
+
+
+def rank_sweep(R, rmax, colscale=None, stream=None):
+    """(K, resid, H, info): SPA's rmax picks and the relative residual of the
+    NNLS fit on each prefix K[:r], r = 1..rmax; H is the fit at rmax."""
+    p, n = R.shape
+    Rc, ldr = _colmajor_input(R)
+    K = torch.empty(rmax, dtype=torch.int32, device=R.device)
+    Hb = torch.empty((n, rmax), dtype=torch.float64, device=R.device)
+    resid = torch.empty(rmax, dtype=torch.float64, device=R.device)
+    info = torch.empty(1, dtype=torch.int32, device=R.device)
+    _check("tsnmf_rank_sweep", tsnmf_rank_sweep(Rc, p, n, ldr, colscale, rmax, K, Hb, rmax, resid, info, stream))
+    return K, resid, Hb.t(), info
 
 
 def reserve(max_m, max_n, max_k=0):

@@ -29,7 +29,7 @@ from . import synth, tsnmf
 
 TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.txt")
 HEADER = ("# tsnmf autotune table: tsqr <dtype> <layout> <leaf precision> <ld == n> <n> <floor(log2 m)> "
-          "<leaf_rows> <tree_arity>\n")
+          "<leaf_rows> <tree_arity> <wy_panel>\n")
 
 
 def key(dtype, layout, leaf, ldeq, n, m):
@@ -37,17 +37,17 @@ def key(dtype, layout, leaf, ldeq, n, m):
 
 
 def load(path=None):
-    """The table as {key: (leaf_rows, tree_arity, comment)}."""
+    """The table as {key: (leaf_rows, tree_arity, wy_panel, comment)}."""
     out = {}
     try:
         with open(path or TUNED) as f:
             for line in f:
                 body, _, note = line.partition("#")
                 p = body.split()
-                if len(p) != 9 or p[0] != "tsqr":
+                if len(p) not in (9, 10) or p[0] != "tsqr":
                     continue
                 k = (p[1], p[2], p[3], int(p[4]), int(p[5]), int(p[6]))
-                out[k] = (int(p[7]), int(p[8]), note.strip())
+                out[k] = (int(p[7]), int(p[8]), int(p[9]) if len(p) == 10 else 0, note.strip())
     except OSError:
         pass
     return out
@@ -57,8 +57,8 @@ def save(table, path=None):
     with open(path or TUNED, "w") as f:
         f.write(HEADER)
         for k in sorted(table):
-            leaf_rows, arity, note = table[k]
-            f.write(f"tsqr {k[0]} {k[1]} {k[2]} {k[3]} {k[4]} {k[5]} {leaf_rows} {arity}"
+            leaf_rows, arity, wy, note = table[k]
+            f.write(f"tsqr {k[0]} {k[1]} {k[2]} {k[3]} {k[4]} {k[5]} {leaf_rows} {arity} {wy}"
                     + (f"  # {note}" if note else "") + "\n")
 
 
@@ -75,7 +75,7 @@ def lookup(X, leaf_f64=False, path=None):
     e = load(path).get(key_of(X, leaf_f64))
     if e is None:
         return None
-    return tsnmf.TsqrConfig(leaf_rows=e[0], tree_arity=e[1], rows_per_lane=0)
+    return tsnmf.TsqrConfig(leaf_rows=e[0], tree_arity=e[1], rows_per_lane=0, wy_panel=e[2])
 
 
 def time_config(X, cfg, leaf_f64=False, reps=20):
@@ -102,31 +102,35 @@ def leaf_grid(m):
     return [0] + sorted({max(64, m // p) for p in (512, 1024, 1536, 2048, 3072, 4096)} | {256, 512, 1024})
 
 
-def tune(X, leaf_f64=False, grid=None, arity_grid=None, verbose=True):
+def tune(X, leaf_f64=False, grid=None, arity_grid=None, wy_grid=None, verbose=True):
     m, n = X.shape
     t0, R0 = time_config(X, None, leaf_f64)
     tol = 1e-5 if (X.dtype == torch.float32 and not leaf_f64) else 1e-11
     grid = leaf_grid(m) if grid is None else grid
     if arity_grid is None:
         arity_grid = [0, 8, 12, 16, 20, 24, 32] if n <= 32 else [0]
-    best = (t0, 0, 0)
-    results = [{"leaf_rows": 0, "tree_arity": 0, "ms": t0}]
+    if wy_grid is None:      # blocked (16-column panels) or unblocked trailing update
+        wy_grid = [16, 1] if (X.dtype == torch.float32 and not leaf_f64 and 33 <= n <= 64) else [0]
+    best = (t0, 0, 0, 0)
+    results = [{"leaf_rows": 0, "tree_arity": 0, "wy_panel": 0, "ms": t0}]
     for leaf in grid:
         for ar in arity_grid:
-            if leaf == 0 and ar == 0:
-                continue
-            cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=int(ar), rows_per_lane=0)
-            ms, R = time_config(X, cfg, leaf_f64)
-            err = float((R - R0).abs().max() / R0.abs().max())
-            ok = err <= tol
-            results.append({"leaf_rows": int(leaf), "tree_arity": int(ar), "ms": ms, "err": err, "ok": ok})
-            if verbose:
-                print(f"leaf_rows {leaf:9d} arity {ar:3d}  {ms:8.3f} ms  "
-                      f"{m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}", flush=True)
-            if ok and ms < best[0]:
-                best = (ms, int(leaf), int(ar))
+            for wy in wy_grid:
+                if leaf == 0 and ar == 0 and wy in (0, 16):
+                    continue
+                cfg = tsnmf.TsqrConfig(leaf_rows=int(leaf), tree_arity=int(ar), rows_per_lane=0, wy_panel=int(wy))
+                ms, R = time_config(X, cfg, leaf_f64)
+                err = float((R - R0).abs().max() / R0.abs().max())
+                ok = err <= tol
+                results.append({"leaf_rows": int(leaf), "tree_arity": int(ar), "wy_panel": int(wy), "ms": ms,
+                                "err": err, "ok": ok})
+                if verbose:
+                    print(f"leaf_rows {leaf:9d} arity {ar:3d} wy {wy:2d}  {ms:8.3f} ms  "
+                          f"{m * n * X.element_size() / ms / 1e6:8.1f} GB/s  err {err:.1e}", flush=True)
+                if ok and ms < best[0]:
+                    best = (ms, int(leaf), int(ar), int(wy))
     note = f"{best[0]:.4f} ms against {t0:.4f} ms default"
-    return key_of(X, leaf_f64), (best[1], best[2], note), results
+    return key_of(X, leaf_f64), (best[1], best[2], best[3], note), results
 
 
 def main():

@@ -262,3 +262,21 @@ def test_projection_workload_full_size_sampled(lib):
     assert np.linalg.norm(Ys[rows] - s.Y) / np.linalg.norm(s.Y) <= 1e-5
     assert np.linalg.norm(Yb[rows] - s.Yk) / np.linalg.norm(s.Yk) <= 5e-4
     assert np.linalg.norm(Yb[rows] - s.Y) / np.linalg.norm(s.Y) <= 1e-2
+
+
+@pytest.mark.parametrize("m,k,off", [(100_003, 512, 0), (5, 4, 2 ** 32 - 2), (1_000_000, 64, 777)])
+def test_generator_colsum(lib, m, k, off):
+    """tsnmf_gauss_colsum (G^T 1, the generator alone): against the oracle's
+    column sums of G, entry by entry with the bound of a projection of a column
+    of ones, and against tsnmf_gauss_proj of that column on the vector units."""
+    s = lib.gauss_colsum(m, k, 21, row_offset=off)
+    torch.cuda.synchronize()
+    s = s.cpu().numpy().astype(np.float64)
+    ones = np.ones((m, 1), dtype=np.float32)
+    ref = Sums(ones, 21, cols=all_groups(k), row0=off)
+    assert (np.abs(s - ref.Y[:, 0]) / ref.bound_f32()[:, 0]).max() <= 1.0
+    Yp, _ = _gp(lib, torch.ones((m, 1), dtype=torch.float32, device="cuda"), k, 21, mode=lib.GP_SIMD_F32,
+                row_offset=off)
+    assert (np.abs(s - Yp[:, 0]) / ref.bound_f32()[:, 0]).max() <= 2.0
+    assert lib.tsnmf_gauss_colsum(0, k, 21, 0, torch.empty(k, device="cuda")) == -1
+    assert lib.tsnmf_gauss_colsum(m, 6, 21, 0, torch.empty(k, device="cuda")) == -2

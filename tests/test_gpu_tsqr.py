@@ -461,3 +461,93 @@ def test_widest_fp32_input_fp64_leaves_and_short(lib):
         X64 = Xs.cpu().numpy().astype(np.float64)
         assert np.all(np.tril(Rg, -1) == 0.0) and np.all(np.diag(Rg) >= 0.0)
         assert _rel_gram(Rg, X64) <= 1e-6
+
+
+@pytest.mark.parametrize("n,layout,leaf_rows", [(33, "col", 0), (40, "row", 2048), (48, "col", 2048),
+                                                (49, "row", 0), (64, "col", 2048), (64, "row", 1536),
+                                                (57, "padded", 2048), (64, "col", 777)])
+def test_wy_leaf_matches_oracle_and_unblocked(lib, n, layout, leaf_rows):
+    """The blocked compact-WY leaf (FP32 row blocks, 33..64 columns, 16-column
+    panels with the trailing update on the matrix cores): R against the oracle,
+    and against the unblocked leaf on the same input (both compute the same R
+    up to rounding).  Slabs of several 512-row blocks, a slab height that is
+    not a whole number of blocks, and ragged last blocks."""
+    m = 100_003
+    X, _ = _layout_view(None, m, n, layout, torch.float32, 600 + n)
+    cfg = lib.TsqrConfig(leaf_rows=leaf_rows, tree_arity=0, rows_per_lane=0, wy_panel=16)
+    Rg, csg = _run(lib, X, config=cfg)
+    _check_against_oracle(Rg, csg, X.cpu().numpy(), 1e-6, 2e-5, 1e-6, norm_tol=1e-5)
+    cfg1 = lib.TsqrConfig(leaf_rows=leaf_rows, tree_arity=0, rows_per_lane=0, wy_panel=1)
+    Ru, _ = _run(lib, X, config=cfg1)
+    assert np.abs(Rg - Ru).max() <= 2e-5 * np.abs(Ru).max()
+
+
+@pytest.mark.parametrize("m,n", [(1, 40), (10, 64), (63, 64), (64, 33), (511, 48), (513, 64)])
+def test_wy_leaf_short_inputs(lib, m, n):
+    X = synth.random_matrix(n, m, dtype=torch.float32, seed_tag=610, dist="uniform").cuda().t()
+    Rg, csg = _run(lib, X, config=lib.TsqrConfig(leaf_rows=0, tree_arity=0, rows_per_lane=0, wy_panel=16))
+    X64 = X.cpu().numpy().astype(np.float64)
+    assert np.all(np.tril(Rg, -1) == 0.0) and np.all(np.diag(Rg) >= 0.0)
+    assert _rel_gram(Rg, X64) <= 1e-6
+    d = np.abs(X64).sum(0)
+    assert np.max(np.abs(csg - d) / d) <= 1e-6
+
+
+def test_wy_panel_argument(lib):
+    X = torch.zeros((100, 40), dtype=torch.float32, device="cuda")
+    R = torch.empty((40, 40), dtype=torch.float64, device="cuda")
+    for bad in (2, 8, 32, -1):
+        cfg = lib.TsqrConfig(leaf_rows=0, tree_arity=0, rows_per_lane=0, wy_panel=bad)
+        assert lib.tsnmf_tsqr_r_ex(X, 100, 40, 40, lib.F32, R, None, cfg) == -8
+
+
+@pytest.mark.parametrize("p,q", [(3162, 5), (2000, 4), (1500, 3), (777, 2), (1000, 1)])
+def test_kron_matches_explicit_bit_for_bit(lib, p, q):
+    """tsnmf_tsqr_r_kron forms each row of X = A (x) A from two rows of A, with
+    the plan of the explicit FP32 X: R and the column sums equal those of
+    tsnmf_tsqr_r on the explicit matrix bit for bit, and R = R_A (x) R_A to
+    FP32 accuracy (the products are rounded to FP32 once, as in X)."""
+    A = torch.from_numpy(synth.kron_factor(p, 5)[:, :q].copy()).cuda()
+    X = torch.kron(A, A).contiguous()
+    Re, ce = lib.tsqr_r(X)
+    Rk, ck = lib.tsqr_r_kron(A)
+    torch.cuda.synchronize()
+    assert torch.equal(Re, Rk) and torch.equal(ce, ck)
+    Ah = A.cpu().numpy().astype(np.float64)
+    RA = np.linalg.qr(Ah, mode="r")
+    RA[np.diag(RA) < 0, :] *= -1
+    Rkh = Rk.cpu().numpy()
+    assert np.abs(Rkh - np.kron(RA, RA)).max() <= 2e-5 * np.abs(RA).max() ** 2
+    dA = np.abs(Ah).sum(0)
+    assert np.max(np.abs(ck.cpu().numpy() - np.kron(dA, dA)) / np.kron(dA, dA)) <= 1e-6
+
+
+@pytest.mark.timeout(300)
+def test_kron_paper_flow_cytometry_size(lib):
+    """The Sec. 5.2 size: A of 40,000 cells x 5 markers, X = A (x) A with
+    1.6e9 rows x 25 columns (160 GB in FP32, never formed).  R against the
+    closed form R_A (x) R_A and the Gram identity R^T R = (A^T A) (x) (A^T A),
+    column sums against d_A (x) d_A."""
+    A = torch.from_numpy(synth.kron_factor(40_000, 5)).cuda()
+    Rk, ck = lib.tsqr_r_kron(A)
+    torch.cuda.synchronize()
+    Ah = A.cpu().numpy().astype(np.float64)
+    RA = np.linalg.qr(Ah, mode="r")
+    RA[np.diag(RA) < 0, :] *= -1
+    R = Rk.cpu().numpy()
+    assert np.all(np.tril(R, -1) == 0.0) and np.all(np.diag(R) >= 0.0)
+    G = np.kron(Ah.T @ Ah, Ah.T @ Ah)
+    assert np.linalg.norm(R.T @ R - G) / np.linalg.norm(G) <= 1e-6
+    assert np.abs(R - np.kron(RA, RA)).max() <= 2e-5 * np.abs(RA).max() ** 2
+    dA = np.abs(Ah).sum(0)
+    assert np.max(np.abs(ck.cpu().numpy() - np.kron(dA, dA)) / np.kron(dA, dA)) <= 1e-6
+
+
+def test_kron_argument_errors(lib):
+    A = torch.ones((10, 5), dtype=torch.float32, device="cuda")
+    R = torch.empty((25, 25), dtype=torch.float64, device="cuda")
+    assert lib.tsnmf_tsqr_r_kron(None, 10, 5, 5, R) == -1
+    assert lib.tsnmf_tsqr_r_kron(A, 0, 5, 5, R) == -2
+    assert lib.tsnmf_tsqr_r_kron(A, 10, 6, 6, R) == -3
+    assert lib.tsnmf_tsqr_r_kron(A, 10, 5, 4, R) == -4
+    assert lib.tsnmf_tsqr_r_kron(A, 10, 5, 5, None) == -5

@@ -24,18 +24,20 @@ def test_key_buckets_by_log2_rows(tune):
 
 
 def test_save_and_load_round_trip(tune):
-    t = {("f32", "row", "f32", 1, 25, 23): (4883, 16, "0.40 ms"),
-         ("f32", "row", "f64", 0, 25, 23): (1000, 0, "")}
+    t = {("f32", "row", "f32", 1, 25, 23): (4883, 16, 0, "0.40 ms"),
+         ("f32", "row", "f64", 0, 25, 23): (1000, 0, 0, ""),
+         ("f32", "col", "f32", 1, 64, 25): (0, 0, 16, "")}
     tune.save(t)
     assert tune.load() == t
     txt = open(tune.TUNED).read()
-    assert "tsqr f32 row f32 1 25 23 4883 16" in txt and "tsqr f32 row f64 0 25 23 1000 0" in txt
+    assert "tsqr f32 row f32 1 25 23 4883 16 0" in txt and "tsqr f32 row f64 0 25 23 1000 0 0" in txt
+    assert "tsqr f32 col f32 1 64 25 0 0 16" in txt
 
 
 def test_leaf_precision_and_contiguity_are_separate_keys(tune):
     """An entry measured on FP32 row blocks is not applied to the FP64-leaf
     kernels, nor to strided rows."""
-    tune.save({("f32", "row", "f32", 1, 25, 23): (4883, 16, "")})
+    tune.save({("f32", "row", "f32", 1, 25, 23): (4883, 16, 0, "")})
     tab = tune.load()
     assert ("f32", "row", "f64", 1, 25, 23) not in tab
     assert ("f32", "row", "f32", 0, 25, 23) not in tab
@@ -57,13 +59,15 @@ def _lib():
 def test_library_parser_accepts_the_table_and_rejects_bad_lines(tmp_path):
     so = _lib()
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n\ntsqr f32 row f32 1 25 23 4883 16  # 0.40 ms\ntsqr f64 col f64 0 64 20 0 0\n")
+    good.write_text("# comment\n\ntsqr f32 row f32 1 25 23 4883 16  # 0.40 ms\ntsqr f64 col f64 0 64 20 0 0\n"
+                    "tsqr f32 col f32 1 64 25 0 0 16\n")
     assert so.tsnmf_tune_load(str(good).encode()) == 0
     for bad in ("tsqr f32 row f32 1 25 23 4883\n",        # missing field
                 "tsqr f16 row f32 1 25 23 4883 16\n",     # dtype
                 "tsqr f64 row f32 1 25 23 0 0\n",         # FP64 input with FP32 leaves
                 "tsqr f32 row f32 1 500 23 0 0\n",        # width
                 "tsqr f32 row f32 1 25 23 0 1\n",         # arity 1
+                "tsqr f32 col f32 1 64 25 0 0 8\n",       # WY panel width
                 "batch s16 4096\n"):                      # unknown kind
         p = tmp_path / "bad.txt"
         p.write_text(bad)

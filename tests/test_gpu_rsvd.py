@@ -1,0 +1,131 @@
+"""GPU parity of tsnmf_rsvd (Sec. 3.1, the SVD of R) and tsnmf_rank_sweep
+(Sec. 2.2 and Sec. 2.4: residuals of many candidate ranks in the reduced
+space) against oracle.rsvd, through the C ABI.
+
+Singular values: one-sided Jacobi and LAPACK both find them to a few ulps of
+s_max; the bound is 1e-13 s_max + 1e-12 s_i.  Right singular vectors of
+singular values separated by a gap g agree up to sign to about eps s_max / g:
+1 - |<v_gpu, v_oracle>| is checked against that, and each GPU vector's sign
+convention (largest-magnitude entry positive) is checked on its own.  Rank
+sweep: K bit-identical to the oracle's SPA on the same R up to the first pick
+whose relative margin is under 1e-9 or whose score is at the rounding level
+(picks past the planted rank on exactly separable data are decided by
+rounding noise), residuals within 1e-10
+relative (+1e-22 absolute) on those prefixes, and a non-increasing curve."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rsvd as orsvd
+from oracle import select as osel
+from oracle import tsqr as otsqr
+from paper_1402_6964_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _spa_margins(M, K, colscale):
+    """Relative margin (best - runner-up) / best of each SPA pick, oracle order."""
+    Z = np.asarray(M, dtype=np.float64) / np.asarray(colscale)[None, :]
+    out, chosen = [], []
+    for j in K:
+        s = np.sum(Z * Z, axis=0)
+        s[chosen] = -np.inf
+        top = np.sort(s)[::-1]
+        out.append((top[0] - top[1]) / top[0] if len(top) > 1 else 1.0)
+        chosen.append(j)
+        u = Z[:, j] / np.sqrt(s[j])
+        Z = Z - np.outer(u, u @ Z)
+    return np.asarray(out)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 25, 64, 128, 200, 256])
+def test_rsvd_matches_oracle(lib, n):
+    rng = np.random.default_rng([71, n])
+    X = rng.lognormal(size=(4 * n + 50, n))
+    R = otsqr.tsqr_r_final(X, leaf_rows=4 * n + 50)
+    print(f"rsvd n={n}", flush=True)
+    S, U, V, info = lib.rsvd(_cuda(R))
+    torch.cuda.synchronize()
+    so, _, Vo = orsvd.rsvd(R)
+    Sg = S.cpu().numpy()
+    assert np.all(np.abs(Sg - so) <= 1e-13 * so[0] + 1e-12 * so)
+    assert 1 <= int(info.item()) <= 40
+    Ug, Vg = U.cpu().numpy(), V.cpu().numpy()
+    assert np.abs(Ug @ np.diag(Sg) @ Vg.T - R).max() <= 1e-12 * so[0]
+    assert np.abs(Vg.T @ Vg - np.eye(n)).max() <= 1e-12
+    assert np.abs(Ug.T @ Ug - np.eye(n)).max() <= 1e-10
+    big = np.argmax(np.abs(Vg), axis=0)
+    assert np.all(Vg[big, np.arange(n)] > 0)
+    gap = np.minimum(np.r_[np.inf, -np.diff(so)], np.r_[-np.diff(so), np.inf])
+    sep = gap > 1e-6 * so[0]
+    dots = np.abs(np.sum(Vg * Vo, axis=0))
+    assert np.all((1.0 - dots)[sep] <= np.maximum(1e-12, (1e-13 * so[0] / gap[sep]) ** 2 * 10))
+
+
+def test_rsvd_kronecker_closed_form(lib):
+    """sigma(A (x) A) = sigma(A) (x) sigma(A), on the R of the GPU's implicit
+    Kronecker TSQR (the Sec. 5.2 construction, 10 million rows)."""
+    A = torch.from_numpy(synth.kron_factor(3162, 5)).cuda()
+    R, _ = lib.tsqr_r_kron(A)
+    S, _, _, info = lib.rsvd(R, with_u=False)
+    torch.cuda.synchronize()
+    sa = np.linalg.svd(A.cpu().numpy().astype(np.float64), compute_uv=False)
+    ref = np.sort(np.kron(sa, sa))[::-1]
+    assert int(info.item()) > 0
+    # X's entries are products rounded to FP32 and the leaves are FP32: a
+    # normwise perturbation of X of a few 1e-7 ||X||, so each singular value
+    # moves by at most that much of s_max (Weyl)
+    assert np.abs(S.cpu().numpy() - ref).max() <= 5e-6 * ref[0]
+
+
+@pytest.mark.parametrize("noisy", [False, True])
+def test_rank_sweep_matches_oracle(lib, noisy):
+    """The Sec. 4 example at m = 20,000 (n = 200, planted r = 20): the residual
+    curve for r = 1..24 on the GPU's R and column sums."""
+    d = synth.paper_example(20_000, noisy=noisy)
+    R, cs = lib.tsqr_r(d["X"].cuda())
+    K, res, H, info = lib.rank_sweep(R, 24, colscale=cs)
+    torch.cuda.synchronize()
+    Rh, csh = R.cpu().numpy(), cs.cpu().numpy()
+    Ko, reso = orsvd.rank_sweep(Rh, 24, colscale=csh)
+    assert len(Ko) == 24 and int(info.item()) == 24
+    # a pick is decided by the data while its margin is clear and its score
+    # is above the rounding level (past the planted rank of exactly separable
+    # data the residual is rounding noise, which differs between the two)
+    _, sco, _ = osel.spa(Rh, 24, colscale=csh)
+    amb = (_spa_margins(Rh, Ko, csh) <= 1e-9) | (np.asarray(sco) <= 1e-20 * sco[0])
+    t = int(np.argmax(amb)) if np.any(amb) else len(Ko)
+    assert t >= 20
+    Kg = K.cpu().tolist()
+    assert Kg[:t] == Ko[:t]
+    assert sorted(Kg[:20]) == d["K"]
+    resg = res.cpu().numpy()
+    assert np.all(np.abs(resg[:t] - reso[:t]) <= 1e-10 * reso[:t] + 1e-22)
+    assert np.all(np.isfinite(resg)) and np.all(resg >= 0.0)
+    assert np.all(resg[1:] <= resg[:-1] * (1 + 1e-9) + 1e-22)
+    if noisy:
+        assert 0.0 < resg[19] < 1e-6
+    else:
+        assert resg[19] < 1e-20
+    # H is the fit at rmax, on R's columns K
+    Hh = H.cpu().numpy()
+    assert Hh.shape == (24, 200) and np.all(Hh >= 0.0)
+
+
+def test_argument_errors(lib):
+    R = torch.eye(4, dtype=torch.float64, device="cuda")
+    S = torch.empty(4, dtype=torch.float64, device="cuda")
+    assert lib.tsnmf_rsvd(None, 4, 4, S, R, 4) == -1
+    assert lib.tsnmf_rsvd(R, 300, 300, S, R, 300) == -2
+    assert lib.tsnmf_rsvd(R, 4, 4, S, R, 3) == -6
+    K = torch.empty(4, dtype=torch.int32, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 5, K, R, 4, S, info) == -6
+    assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 4, K, R, 3, S, info) == -9
+    assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 4, K, R, 4, S, None) == -11

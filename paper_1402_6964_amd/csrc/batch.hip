@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "tsqr_coop.hpp"
 #include "tsqr_small_inst.hpp"
 #include "tsqr_wide.hpp"
 

@@ -56,7 +56,7 @@ __device__ __forceinline__ void gauss4(int64_t i, uint32_t q, uint32_t k0, uint3
     const float ln2 = 0.693147180559945309f;
 #pragma unroll
     for (int t = 0; t < 4; t += 2) {
-        const float rad = __builtin_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u[t]));
+        const float rad = __builtin_amdgcn_sqrtf(-2.0f * ln2 * __builtin_amdgcn_logf(u[t]));
         g[t] = rad * __builtin_amdgcn_cosf(u[t + 1]);
         g[t + 1] = rad * __builtin_amdgcn_sinf(u[t + 1]);
     }
@@ -95,11 +95,18 @@ __device__ __forceinline__ float load_f32(const void* X, int64_t idx, bool bf16)
 // normals go to four different M-tiles (tile s holds columns 4q + s), so every
 // normal is used once.  The 32 x n chunk of X is staged in LDS as BF16,
 // column by column, so that the B operand of lane L (8 consecutive rows of one
-// column) is one 16-byte read.
+// column) is one 16-byte read; a column takes 40 BF16 slots (80 bytes), so the
+// 16 lanes of a read phase, and of the staging writes, cover the 64 banks once.
+// The chunk after the current one is loaded into registers while the current
+// one is generated and multiplied, and the staging is double-buffered, so one
+// barrier per chunk orders writes and reads and the loads' latency is hidden
+// behind the generator.
 constexpr int kMfmaRows = 32;
+constexpr int kXsStride = 40;                        // BF16 slots per staged column
 
-__global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
-    __shared__ __align__(16) __bf16 xs[128 * kMfmaRows];   // [column][row]
+template <bool BF16_IN>
+__global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
+    __shared__ __align__(16) __bf16 xs[2][128 * kXsStride];   // [buffer][column][row]
     __shared__ double cs_sh[4][128];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
@@ -120,21 +127,40 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
     double csum = 0.0;                               // sums of column col_ld over this thread's rows
     const int col_ld = tid & 127;                    // staging: column handled by this thread
     const int rgrp = tid >> 7;                       // rows 8 rgrp .. 8 rgrp + 7 of the chunk
-    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows) {
-        __syncthreads();
-        if (col_ld < n) {
-            // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply
-            // per chunk, then one add per row
-            const int64_t ib = i0 + rgrp * 8;
-            int64_t idx = ib * a.ld + cb + col_ld;
+    const bool stager = col_ld < n;
+    // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply per
+    // chunk, then one add per row
+    float v[8];
+    auto load_chunk = [&](int64_t i0) {
+        const int64_t ib = i0 + rgrp * 8;
+        int64_t idx = ib * a.ld + cb + col_ld;
+        if (stager && ib + 8 <= r1) {                // whole 8-row group: no per-row masks
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const float v = ib + t < r1 ? load_f32(a.X, idx, bf16_in) : 0.0f;
+                v[t] = load_f32(a.X, idx, BF16_IN);
                 idx += a.ld;
-                csum += (double)__builtin_fabsf(v);
-                xs[col_ld * kMfmaRows + rgrp * 8 + t] = (__bf16)v;   // round to nearest even
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                v[t] = stager && ib + t < r1 ? load_f32(a.X, idx, BF16_IN) : 0.0f;
+                idx += a.ld;
             }
         }
+    };
+    load_chunk(r0);
+    int buf = 0;
+    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows, buf ^= 1) {
+        if (stager) {
+            bf16x8 pk;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                csum += (double)__builtin_fabsf(v[t]);
+                pk[t] = (__bf16)v[t];                // round to nearest even
+            }
+            *(bf16x8*)(xs[buf] + col_ld * kXsStride + rgrp * 8) = pk;
+        }
+        if (i0 + kMfmaRows < r1) load_chunk(i0 + kMfmaRows);
         __syncthreads();
         bf16x8 av[4];
 #pragma unroll
@@ -148,7 +174,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
         for (int nt = 0; nt < 8; ++nt) {
             if (nt < NT) {
                 const int c = nt * 16 + (L & 15);
-                const bf16x8 b = c < n ? *(const bf16x8*)(xs + c * kMfmaRows + 8 * (L >> 4)) : bf16x8{};
+                const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + 8 * (L >> 4)) : bf16x8{};
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], b, acc[s][nt], 0, 0, 0);
@@ -169,6 +195,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a, int bf16_in) {
             }
         }
     if (a.part_cs != nullptr && blockIdx.y == 0) {
+        __syncthreads();
         cs_sh[rgrp][col_ld] = csum;
         __syncthreads();
         if (tid < n)
@@ -391,7 +418,8 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
         if (int st = profile_event(stream, &e0)) return st;
     }
     if (mfma) {
-        hipLaunchKernelGGL(gp_mfma_kernel, grid, dim3(512), 0, stream, a, bf16 ? 1 : 0);
+        if (bf16) hipLaunchKernelGGL(gp_mfma_kernel<true>, grid, dim3(512), 0, stream, a);
+        else hipLaunchKernelGGL(gp_mfma_kernel<false>, grid, dim3(512), 0, stream, a);
     } else {
         hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
     }

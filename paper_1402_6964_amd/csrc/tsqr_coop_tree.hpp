@@ -3,6 +3,7 @@
 // leaves, later levels by ticket.  Instantiated in tsqr_coop_tree_*.hip,
 // eight widths per file so that they compile in parallel.
 #pragma once
+#include "tsqr_coop.hpp"
 #include "tsqr_small_inst.hpp"
 
 namespace tsnmf {

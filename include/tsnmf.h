@@ -370,6 +370,95 @@ int tsnmf_rank_sweep(const double* R, int32_t p, int32_t n, int32_t ldr, const d
                      int32_t rmax, int32_t* K, double* H, int32_t ldh, double* resid, int32_t* info,
                      hipStream_t stream);
 
+/* ---- one pass over a matrix delivered in row blocks -------------------------------- */
+
+/*
+ * A tsnmf_onepass_t holds the state of one pass over a tall matrix X whose
+ * rows arrive in consecutive blocks, possibly from host memory and in total
+ * larger than device memory (Sec. 4 and Sec. 5.1 work on 286 GB and 2 TB
+ * matrices read from disk; the method reads the data once, Sec. 3.3 and
+ * Sec. 3.5).  For every block it computes, in the same pass over the block:
+ * the block's R factor and column sums (as tsnmf_tsqr_r) and, when k > 0, the
+ * block's share of G^T X with the rows of G that the block's global row
+ * indices select (as tsnmf_gauss_proj with row_offset = rows pushed before),
+ * so TSQR and the projection read the data once together (Sec. 3.5: the
+ * projection cannot give H in the projected space, so R is computed in the
+ * same pass).  The device state is the running FP64 R (the block's R and the
+ * running R are merged by an FP64 QR of the two stacked factors: one more
+ * node of the reduction tree), the FP64 column sums and FP64 G^T X: O(n^2 +
+ * k n) doubles whatever the number of rows, a complete resumable state
+ * (tsnmf_onepass_save / _load).
+ *
+ * tsnmf_onepass_create: new state for n columns.
+ *   n       1..TSNMF_MAX_N.
+ *   flags   TSNMF_F32 or TSNMF_F64 | TSNMF_ROW_MAJOR or TSNMF_COL_MAJOR
+ *           [| TSNMF_LEAF_F64] [| TSNMF_GP_MFMA_BF16 or TSNMF_GP_SIMD_F32];
+ *           with k > 0 the input must be TSNMF_F32, TSNMF_ROW_MAJOR.
+ *   k       0 (no projection) or as tsnmf_gauss_proj (multiple of 4, 4..4096).
+ *   seed    key of the projection's generator.
+ *   out     host pointer that receives the handle.
+ * Allocates the state and two 64 MiB device blocks for host input.  Host call.
+ * Errors: -1 n, -2 flags, -3 k, -5 out; TSNMF_ERR_NOMEM, TSNMF_ERR_HIP.
+ */
+typedef struct tsnmf_onepass_s* tsnmf_onepass_t;
+int tsnmf_onepass_create(int32_t n, uint32_t flags, int32_t k, uint64_t seed, tsnmf_onepass_t* out);
+
+/*
+ * tsnmf_onepass_push: the next `rows` rows of X, in device memory (dtype and
+ * layout of the create flags; ld >= n row-major, >= rows column-major).
+ * Enqueued on `stream`; the block must stay valid until the stream reaches
+ * the end of the call's work.  Pushes to one state must be ordered (one
+ * stream, or synchronised streams); the library workspace is shared as in
+ * tsnmf_tsqr_r.  Errors: -1 state, -2 X, -3 rows < 1, -4 ld.
+ */
+int tsnmf_onepass_push(tsnmf_onepass_t p, const void* X, int64_t rows, int64_t ld, hipStream_t stream);
+
+/*
+ * tsnmf_onepass_push_host: the next `rows` rows of X in HOST memory
+ * (row-major only, ld >= n), e.g. a memory-mapped file.  The rows go to the
+ * device in blocks of tsnmf_onepass_block_rows() rows through two device
+ * buffers: the copy of one block (on a copy stream of the library) overlaps
+ * the work on the previous one (on `stream`).  Pinned host memory (allocated
+ * by hipHostMalloc) is copied by DMA directly; pageable memory is first
+ * copied by host threads into pinned staging buffers.  Returns when every
+ * row has been handed to the copy engine (X may then be reused); the work
+ * completes on `stream`.  The result equals that of tsnmf_onepass_push called
+ * with the same blocks.  Errors: -1 state, -2 X, -3 rows < 1, -4 ld,
+ * TSNMF_ERR_UNSUPPORTED for a column-major state.
+ */
+int tsnmf_onepass_push_host(tsnmf_onepass_t p, const void* X, int64_t rows, int64_t ld, hipStream_t stream);
+
+/* Rows per device block of tsnmf_onepass_push_host (host value), and rows
+   pushed so far.  Errors: -1 state, -2 out. */
+int tsnmf_onepass_block_rows(tsnmf_onepass_t p, int64_t* rows);
+int tsnmf_onepass_rows(tsnmf_onepass_t p, int64_t* rows);
+
+/*
+ * tsnmf_onepass_result: results over all rows pushed so far (the state is
+ * unchanged; more rows may follow).
+ *   R       device FP64 n x n column-major output (diag >= 0, R^T R = X^T X)
+ *   colsum  device FP64[n] output or NULL
+ *   Y       device FP32 k x n column-major output (G^T X) or NULL
+ * Before any push, R, colsum and Y are zero.  Errors: -1 state, -2 R.
+ */
+int tsnmf_onepass_result(tsnmf_onepass_t p, double* R, double* colsum, float* Y, hipStream_t stream);
+
+/*
+ * Resumable state: tsnmf_onepass_state_bytes gives the size of the saved
+ * state; tsnmf_onepass_save writes it to HOST memory `host` (a header with n,
+ * k, flags, seed and the rows pushed, then R, the column sums and G^T X in
+ * FP64) after waiting for `stream`; tsnmf_onepass_load restores it into a
+ * state created with the same n, flags, k and seed (else -2), after which
+ * pushes continue exactly where the saved pass stopped.  Errors: -1 state,
+ * -2 host buffer or mismatching header, -3 (bytes) too small.
+ */
+int tsnmf_onepass_state_bytes(tsnmf_onepass_t p, size_t* bytes);
+int tsnmf_onepass_save(tsnmf_onepass_t p, void* host, size_t bytes, hipStream_t stream);
+int tsnmf_onepass_load(tsnmf_onepass_t p, const void* host, size_t bytes, hipStream_t stream);
+
+/* Frees the state (waits for its pending work).  Errors: -1 state. */
+int tsnmf_onepass_destroy(tsnmf_onepass_t p);
+
 /* ---- housekeeping ------------------------------------------------------------------- */
 
 /* Grow the current device's workspace so that TSQR calls with m <= max_m and

@@ -64,7 +64,7 @@ int nnls_impl(const double* M, int p, int n, int ldm, const int* K, int r, doubl
 int residual_impl(const double* M, int p, int n, int ldm, const int* K, int r, const double* H, int ldh,
                   double* relerr, hipStream_t stream);
 int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
-                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream);
+                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream, double* yacc = nullptr);
 int tsqr_r_kron_impl(const float* A, int64_t p, int q, int64_t lda, double* R, double* colsum, hipStream_t stream);
 int rsvd_impl(const double* R, int n, int ldr, double* S, double* V, int ldv, double* U, int ldu, int* info,
               hipStream_t stream);

@@ -327,14 +327,19 @@ __global__ void __launch_bounds__(512) gp_colsum_kernel(GpArgs a) {
 }
 
 // Sum of the workgroup partials in FP64, in workgroup order; Y column-major.
+// With `yacc` set, the FP64 sums are added to yacc (k x n column-major,
+// FP64) instead of being written to Y: a pass over row blocks accumulates
+// G^T X block by block.
 __global__ void gp_reduce_kernel(const float* __restrict__ part, int64_t nparts, int k, int n, float* __restrict__ Y,
-                                 const double* __restrict__ part_cs, double* __restrict__ colsum) {
+                                 const double* __restrict__ part_cs, double* __restrict__ colsum,
+                                 double* __restrict__ yacc) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // index l * n + c
     if (t < (int64_t)k * n) {
         double s = 0.0;
         for (int64_t p = 0; p < nparts; ++p) s += (double)part[p * k * n + t];
         const int l = (int)(t / n), c = (int)(t % n);
-        Y[(int64_t)c * k + l] = (float)s;
+        if (yacc != nullptr) yacc[(int64_t)c * k + l] += s;
+        else Y[(int64_t)c * k + l] = (float)s;
     }
     if (colsum != nullptr && t < n) {
         double s = 0.0;
@@ -377,7 +382,7 @@ int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float
         profile_record(0, e0, e1);
     }
     hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, a.part, parts, k, 1,
-                       out, nullptr, nullptr);
+                       out, nullptr, nullptr, nullptr);
     TSNMF_LAUNCH_CHECK();
     return TSNMF_OK;
 }
@@ -389,7 +394,7 @@ size_t gp_workspace_bytes(int64_t m, int n, int k) {
 }
 
 int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, int k, uint64_t seed,
-                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream) {
+                    int64_t row_offset, float* Y, double* colsum, hipStream_t stream, double* yacc) {
     const bool bf16 = (flags & TSNMF_DTYPE_MASK) == TSNMF_BF16;
     const bool mfma = bf16 || (flags & TSNMF_GP_MFMA_BF16) != 0;
     const int rows_multiple = mfma ? kMfmaRows : kSimdRows;
@@ -433,7 +438,7 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
     }
     const int64_t outs = (int64_t)k * n;
     hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream, a.part, parts, k,
-                       n, Y, a.part_cs, colsum);
+                       n, Y, a.part_cs, colsum, yacc);
     TSNMF_LAUNCH_CHECK();
     if (prof_all) {
         if (int st = profile_event(stream, &e3)) return st;

@@ -83,6 +83,16 @@ _residual = _sig("tsnmf_residual", ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i
 _rsvd = _sig("tsnmf_rsvd", ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp])
 _rank_sweep = _sig("tsnmf_rank_sweep", ctypes.c_int,
                    [_vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp])
+_onepass_create = _sig("tsnmf_onepass_create", ctypes.c_int, [_i32, _u32, _i32, _u64, ctypes.POINTER(_vp)])
+_onepass_push = _sig("tsnmf_onepass_push", ctypes.c_int, [_vp, _vp, _i64, _i64, _vp])
+_onepass_push_host = _sig("tsnmf_onepass_push_host", ctypes.c_int, [_vp, _vp, _i64, _i64, _vp])
+_onepass_block_rows = _sig("tsnmf_onepass_block_rows", ctypes.c_int, [_vp, ctypes.POINTER(_i64)])
+_onepass_rows = _sig("tsnmf_onepass_rows", ctypes.c_int, [_vp, ctypes.POINTER(_i64)])
+_onepass_result = _sig("tsnmf_onepass_result", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
+_onepass_state_bytes = _sig("tsnmf_onepass_state_bytes", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)])
+_onepass_save = _sig("tsnmf_onepass_save", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp])
+_onepass_load = _sig("tsnmf_onepass_load", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp])
+_onepass_destroy = _sig("tsnmf_onepass_destroy", ctypes.c_int, [_vp])
 _reserve = _sig("tsnmf_reserve", ctypes.c_int, [_i64, _i32, _i32])
 _workspace_release = _sig("tsnmf_workspace_release", ctypes.c_int, [])
 _tune_load = _sig("tsnmf_tune_load", ctypes.c_int, [ctypes.c_char_p])
@@ -108,7 +118,9 @@ def _ptr(t):
         return None
     if isinstance(t, int):
         return t
-    return t.data_ptr()
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data              # numpy array (host memory)
 
 
 def _stream(stream):
@@ -188,6 +200,47 @@ def tsnmf_rsvd(R, n, ldr, S, V, ldv, U=None, ldu=0, info=None, stream=None):
 def tsnmf_rank_sweep(R, p, n, ldr, colscale, rmax, K, H, ldh, resid, info, stream=None):
     return _rank_sweep(_ptr(R), p, n, ldr, _ptr(colscale), rmax, _ptr(K), _ptr(H), ldh, _ptr(resid), _ptr(info),
                        _stream(stream))
+
+
+def tsnmf_onepass_create(n, flags, k, seed, out):
+    """`out` is a ctypes.c_void_p that receives the handle."""
+    return _onepass_create(n, flags, k, seed, ctypes.byref(out))
+
+
+def tsnmf_onepass_push(p, X, rows, ld, stream=None):
+    return _onepass_push(p, _ptr(X), rows, ld, _stream(stream))
+
+
+def tsnmf_onepass_push_host(p, X, rows, ld, stream=None):
+    return _onepass_push_host(p, _ptr(X), rows, ld, _stream(stream))
+
+
+def tsnmf_onepass_block_rows(p, out):
+    return _onepass_block_rows(p, ctypes.byref(out))
+
+
+def tsnmf_onepass_rows(p, out):
+    return _onepass_rows(p, ctypes.byref(out))
+
+
+def tsnmf_onepass_result(p, R, colsum=None, Y=None, stream=None):
+    return _onepass_result(p, _ptr(R), _ptr(colsum), _ptr(Y), _stream(stream))
+
+
+def tsnmf_onepass_state_bytes(p, out):
+    return _onepass_state_bytes(p, ctypes.byref(out))
+
+
+def tsnmf_onepass_save(p, host, nbytes, stream=None):
+    return _onepass_save(p, _ptr(host), nbytes, _stream(stream))
+
+
+def tsnmf_onepass_load(p, host, nbytes, stream=None):
+    return _onepass_load(p, _ptr(host), nbytes, _stream(stream))
+
+
+def tsnmf_onepass_destroy(p):
+    return _onepass_destroy(p)
 
 
 def tsnmf_reserve(max_m, max_n, max_k=0):
@@ -390,6 +443,71 @@ def rank_sweep(R, rmax, colscale=None, stream=None):
     info = torch.empty(1, dtype=torch.int32, device=R.device)
     _check("tsnmf_rank_sweep", tsnmf_rank_sweep(Rc, p, n, ldr, colscale, rmax, K, Hb, rmax, resid, info, stream))
     return K, resid, Hb.t(), info
+
+
+class OnePass:
+    """One pass over a matrix delivered in row blocks (device tensors or host
+    arrays): R, column sums and, with k > 0, G^T X over all rows pushed."""
+
+    def __init__(self, n, dtype=torch.float32, col_major=False, k=0, seed=0, mode=None, leaf_f64=False):
+        flags = _DTYPE_FLAG[dtype] | (COL_MAJOR if col_major else ROW_MAJOR) | (LEAF_F64 if leaf_f64 else 0)
+        if k > 0:
+            flags |= GP_SIMD_F32 if mode is None else mode
+        self.n, self.k, self.h = n, k, ctypes.c_void_p()
+        _check("tsnmf_onepass_create", tsnmf_onepass_create(n, flags, k, seed, self.h))
+
+    def push(self, X, stream=None):
+        """A device tensor with the state's dtype and layout (rows x n)."""
+        lay, ld = _layout(X)
+        _check("tsnmf_onepass_push", tsnmf_onepass_push(self.h, X, X.shape[0], ld, stream))
+
+    def push_host(self, X, stream=None):
+        """A row-major host array (numpy array or CPU tensor, pinned or not)."""
+        rows = X.shape[0]
+        ld = X.stride(0) if isinstance(X, torch.Tensor) else X.strides[0] // X.itemsize
+        _check("tsnmf_onepass_push_host", tsnmf_onepass_push_host(self.h, X, rows, ld, stream))
+
+    @property
+    def block_rows(self):
+        v = _i64()
+        _check("tsnmf_onepass_block_rows", tsnmf_onepass_block_rows(self.h, v))
+        return v.value
+
+    @property
+    def rows(self):
+        v = _i64()
+        _check("tsnmf_onepass_rows", tsnmf_onepass_rows(self.h, v))
+        return v.value
+
+    def result(self, stream=None, device="cuda"):
+        n, k = self.n, self.k
+        Rb = torch.empty((n, n), dtype=torch.float64, device=device)
+        cs = torch.empty(n, dtype=torch.float64, device=device)
+        Yb = torch.empty((n, k), dtype=torch.float32, device=device) if k > 0 else None
+        _check("tsnmf_onepass_result", tsnmf_onepass_result(self.h, Rb, cs, Yb, stream))
+        return colmajor_square(Rb), cs, (Yb.t() if k > 0 else None)
+
+    def save(self, stream=None):
+        nb = ctypes.c_size_t()
+        _check("tsnmf_onepass_state_bytes", tsnmf_onepass_state_bytes(self.h, nb))
+        buf = (ctypes.c_char * nb.value)()
+        _check("tsnmf_onepass_save", tsnmf_onepass_save(self.h, ctypes.addressof(buf), nb.value, stream))
+        return bytes(buf)
+
+    def load(self, blob, stream=None):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check("tsnmf_onepass_load", tsnmf_onepass_load(self.h, ctypes.addressof(buf), len(blob), stream))
+
+    def close(self):
+        if self.h.value:
+            _check("tsnmf_onepass_destroy", tsnmf_onepass_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def reserve(max_m, max_n, max_k=0):

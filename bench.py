@@ -8,11 +8,13 @@ A step is one tsnmf_tsqr_r call on the flow-cytometry-shaped workload
 in HBM): row-block Householder leaves with fused l1 column sums, the FP64
 reduction tree and the finalisation of R.  `value` is GB/s of X (bytes of X
 divided by the mean step time).  The line also carries:
-  roofline      the leaf kernel's algorithmic FP32 flops per launch over its
-                mean duration, timed with HIP events recorded by the library
-                on the launch stream during the timed steps, against the
-                78.6 TF/s FP32 vector peak without packed instructions (the
-                kernel's bound); its bytes against 8 TB/s ride along;
+  roofline      the leaf kernel's algorithmic bytes per launch (every
+                element of X once) over its mean duration, timed with HIP
+                events recorded by the library on the launch stream during the
+                timed steps, against 8 TB/s of HBM; `traffic` is the measured
+                HBM bytes per launch from the committed rocprofv3 counter
+                summary when it was taken on the current leaf source; its FP32
+                flops (2 m n^2) against the vector peaks ride along (`alu`);
   cpu_baseline  the CPU oracle (plain FP64 numpy Householder TSQR) timed on
                 this host: over all of X on up to 16 worker processes (the
                 host's CPU count is recorded), and on one thread over a
@@ -24,8 +26,10 @@ divided by the mean step time).  The line also carries:
                 matrices (one graph-captured persistent launch, against one
                 FP64 tsnmf_tsqr_r call per matrix), the heat-transfer-shaped
                 50,000,000 x 64 column-major matrix, the 20,000,000 x 128
-                Gaussian projection (BF16 matrix cores and FP32 vector units),
-                and the 100,000 x 20 FP64 example.
+                Gaussian projection (BF16 matrix cores and FP32 vector units,
+                and its generator alone), the 100,000 x 20 FP64 example, and
+                the one-pass path over 64 MiB row blocks from device, pinned
+                and pageable host memory (host rates include the copies).
 Only one GPU is used: --gpus above 1 exits with a message.
 """
 
@@ -375,6 +379,45 @@ def extras(torch, tsnmf, synth, dev, check=True, tuned=None):
                          "pipeline": "TSQR (1,000-row leaves, binary tree) -> SPA (r = 10) -> NNLS -> residual",
                          "pipeline_us": round(tp * 1e6, 1), "pipeline_graph_us": round(tg * 1e6, 1),
                          "K": sorted(K.cpu().tolist()), "K_planted": d["K"], "residual": float(rel.item())}
+    del X, d
+    torch.cuda.empty_cache()
+
+    # One pass over row blocks (tsnmf_onepass_*), the path for matrices larger
+    # than the device: the flow-cytometry matrix pushed from device memory in
+    # the 64 MiB blocks the host path uses, and from pinned and pageable host
+    # memory (the host rates include the host-to-device copies), with and
+    # without G^T X (k = 32, matrix cores) in the same pass.
+    _note("one pass: flow cytometry in 64 MiB blocks, device and host input")
+    dfc = synth.flow_cytometry(device=dev)
+    Xd = dfc["X"]
+    m, n = Xd.shape
+    Xp = Xd.cpu().pin_memory()
+    Xn = Xd.cpu().numpy()
+    op_out = {"workload": "flow_cytometry 10,000,000 x 25 FP32 row-major (1.0 GB), 64 MiB blocks"}
+
+    def one_pass(kind, k):
+        op = tsnmf.OnePass(n, k=k, seed=14026964, mode=tsnmf.GP_MFMA_BF16 if k else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "device":
+            br = op.block_rows
+            for a in range(0, m, br):
+                op.push(Xd[a:min(m, a + br)])
+        else:
+            op.push_host(Xp if kind == "pinned_host" else Xn)
+        op.result()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        op.close()
+        return t
+
+    for kind, k in (("device", 0), ("pinned_host", 0), ("pageable_host", 0), ("device", 32), ("pinned_host", 32)):
+        one_pass(kind, k)
+        t = min(one_pass(kind, k) for _ in range(3))
+        op_out[f"{kind}_k{k}"] = {"s": round(t, 4), "gbs": round(m * n * 4 / t / 1e9, 2)}
+    out["one_pass"] = op_out
+    del Xd, Xp, Xn, dfc
+    torch.cuda.empty_cache()
     return out
 
 

@@ -419,11 +419,13 @@ int tsnmf_onepass_push(tsnmf_onepass_t p, const void* X, int64_t rows, int64_t l
  * device in blocks of tsnmf_onepass_block_rows() rows through two device
  * buffers: the copy of one block (on a copy stream of the library) overlaps
  * the work on the previous one (on `stream`).  Pinned host memory (allocated
- * by hipHostMalloc) is copied by DMA directly; pageable memory is first
+ * by hipHostMalloc) is copied by DMA directly, or, for a state without
+ * projection (k = 0), read by the leaf kernels over the host link with no
+ * copy at all (the call then waits for `stream`); pageable memory is first
  * copied by host threads into pinned staging buffers.  Returns when every
- * row has been handed to the copy engine (X may then be reused); the work
- * completes on `stream`.  The result equals that of tsnmf_onepass_push called
- * with the same blocks.  Errors: -1 state, -2 X, -3 rows < 1, -4 ld,
+ * row has been copied or read (X may then be reused); the remaining work
+ * completes on `stream`.  The result equals that of tsnmf_onepass_push
+ * called with the same blocks.  Errors: -1 state, -2 X, -3 rows < 1, -4 ld,
  * TSNMF_ERR_UNSUPPORTED for a column-major state.
  */
 int tsnmf_onepass_push_host(tsnmf_onepass_t p, const void* X, int64_t rows, int64_t ld, hipStream_t stream);

@@ -52,7 +52,7 @@ __device__ __forceinline__ void gauss4(int64_t i, uint32_t q, uint32_t k0, uint3
     philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), q, 0u, k0, k1, x);
     float u[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) u[t] = (float)((x[t] >> 8) + 1u) * 0x1p-24f;
+    for (int t = 0; t < 4; ++t) u[t] = __builtin_fmaf((float)(x[t] >> 8), 0x1p-24f, 0x1p-24f);   // exact
     const float ln2 = 0.693147180559945309f;
 #pragma unroll
     for (int t = 0; t < 4; t += 2) {
@@ -162,22 +162,24 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
         }
         if (i0 + kMfmaRows < r1) load_chunk(i0 + kMfmaRows);
         __syncthreads();
-        bf16x8 av[4];
+        if (lbase < k) {                             // waves past k only stage X
+            bf16x8 av[4];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            float g[4];
-            gauss4(a.row_offset + i0 + 8 * (L >> 4) + t, q, a.key0, a.key1, g);
+            for (int t = 0; t < 8; ++t) {
+                float g[4];
+                gauss4(a.row_offset + i0 + 8 * (L >> 4) + t, q, a.key0, a.key1, g);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) av[s][t] = (__bf16)g[s];
-        }
+                for (int s = 0; s < 4; ++s) av[s][t] = (__bf16)g[s];
+            }
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            if (nt < NT) {
-                const int c = nt * 16 + (L & 15);
-                const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + 8 * (L >> 4)) : bf16x8{};
+            for (int nt = 0; nt < 8; ++nt) {
+                if (nt < NT) {
+                    const int c = nt * 16 + (L & 15);
+                    const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + 8 * (L >> 4)) : bf16x8{};
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], b, acc[s][nt], 0, 0, 0);
+                    for (int s = 0; s < 4; ++s)
+                        acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], b, acc[s][nt], 0, 0, 0);
+                }
             }
         }
     }
@@ -235,8 +237,9 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
     int buf = 0;
     for (int64_t i0 = r0; i0 < r1; i0 += kSimdRows, buf ^= 1) {
         {
-            float g[4];
-            gauss4(a.row_offset + i0 + gen_row, (uint32_t)((lbase >> 2) + gen_q), a.key0, a.key1, g);
+            float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // columns past k are not generated
+            if (lbase + 4 * gen_q < k)
+                gauss4(a.row_offset + i0 + gen_row, (uint32_t)((lbase >> 2) + gen_q), a.key0, a.key1, g);
             *(float4*)&gs[buf][gen_row][4 * gen_q] = make_float4(g[0], g[1], g[2], g[3]);
             if (tid < kSimdRows * 128) {
                 const int rr = tid >> 7, c = tid & 127;
@@ -303,7 +306,7 @@ __global__ void __launch_bounds__(512) gp_colsum_kernel(GpArgs a) {
     const int lbase = blockIdx.y * 512 + wv * 64;
     const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows) {
+    for (int64_t i0 = r0; i0 < r1 && lbase < a.k; i0 += kMfmaRows) {   // waves past k idle
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int64_t i = i0 + 8 * (L >> 4) + t;
@@ -326,27 +329,61 @@ __global__ void __launch_bounds__(512) gp_colsum_kernel(GpArgs a) {
     }
 }
 
-// Sum of the workgroup partials in FP64, in workgroup order; Y column-major.
+// Sum of the workgroup partials in FP64; Y column-major.  A workgroup of 16
+// waves takes 64 consecutive outputs: wave w sums the partials of the w-th
+// sixteenth of the workgroups (four interleaved FP64 accumulators, so that
+// loads of different partials are in flight together), and the 16 wave sums
+// are added in wave order, so the order of the additions is fixed.  Outputs
+// past k n are the column sums (from part_cs) when colsum is set.
 // With `yacc` set, the FP64 sums are added to yacc (k x n column-major,
 // FP64) instead of being written to Y: a pass over row blocks accumulates
 // G^T X block by block.
-__global__ void gp_reduce_kernel(const float* __restrict__ part, int64_t nparts, int k, int n, float* __restrict__ Y,
-                                 const double* __restrict__ part_cs, double* __restrict__ colsum,
-                                 double* __restrict__ yacc) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // index l * n + c
-    if (t < (int64_t)k * n) {
-        double s = 0.0;
-        for (int64_t p = 0; p < nparts; ++p) s += (double)part[p * k * n + t];
+constexpr int kReduceWaves = 16;
+
+__global__ void __launch_bounds__(kReduceWaves * 64) gp_reduce_kernel(const float* __restrict__ part, int64_t nparts,
+                                                                     int k, int n, float* __restrict__ Y,
+                                                                     const double* __restrict__ part_cs,
+                                                                     double* __restrict__ colsum,
+                                                                     double* __restrict__ yacc) {
+    __shared__ double red[kReduceWaves][64];
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const int64_t kn = (int64_t)k * n;
+    const int64_t ncs = colsum != nullptr ? n : 0;
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t p0 = nparts * w / kReduceWaves, p1 = nparts * (w + 1) / kReduceWaves;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (t < kn) {
+        int64_t p = p0;
+        for (; p + 4 <= p1; p += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += (double)part[(p + u) * kn + t];
+        }
+        for (; p < p1; ++p) acc[0] += (double)part[p * kn + t];
+    } else if (t < kn + ncs) {
+        const int64_t c = t - kn;
+        int64_t p = p0;
+        for (; p + 4 <= p1; p += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += part_cs[(p + u) * n + c];
+        }
+        for (; p < p1; ++p) acc[0] += part_cs[p * n + c];
+    }
+    red[w][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (w != 0) return;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kReduceWaves; ++q) s += red[q][lane];
+    if (t < kn) {
         const int l = (int)(t / n), c = (int)(t % n);
         if (yacc != nullptr) yacc[(int64_t)c * k + l] += s;
         else Y[(int64_t)c * k + l] = (float)s;
-    }
-    if (colsum != nullptr && t < n) {
-        double s = 0.0;
-        for (int64_t p = 0; p < nparts; ++p) s += part_cs[p * n + t];
-        colsum[t] = s;
+    } else if (t < kn + ncs) {
+        colsum[t - kn] = s;
     }
 }
+
+unsigned reduce_blocks(int64_t outputs) { return (unsigned)((outputs + 63) / 64); }
 
 constexpr int64_t kGpWorkgroups = 2048;
 
@@ -381,8 +418,8 @@ int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float
         if (int st = profile_event(stream, &e1)) return st;
         profile_record(0, e0, e1);
     }
-    hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, stream, a.part, parts, k, 1,
-                       out, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(gp_reduce_kernel, dim3(reduce_blocks(k)), dim3(kReduceWaves * 64), 0, stream, a.part, parts, k,
+                       1, out, nullptr, nullptr, nullptr);
     TSNMF_LAUNCH_CHECK();
     return TSNMF_OK;
 }
@@ -437,8 +474,8 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
             if (int st = profile_event(stream, &e2)) return st;
     }
     const int64_t outs = (int64_t)k * n;
-    hipLaunchKernelGGL(gp_reduce_kernel, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream, a.part, parts, k,
-                       n, Y, a.part_cs, colsum, yacc);
+    hipLaunchKernelGGL(gp_reduce_kernel, dim3(reduce_blocks(outs + (colsum != nullptr ? n : 0))),
+                       dim3(kReduceWaves * 64), 0, stream, a.part, parts, k, n, Y, a.part_cs, colsum, yacc);
     TSNMF_LAUNCH_CHECK();
     if (prof_all) {
         if (int st = profile_event(stream, &e3)) return st;

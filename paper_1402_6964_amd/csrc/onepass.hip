@@ -11,7 +11,8 @@
 // The running state is small (O(n^2 + k n) doubles) and is the whole
 // resumable state of the pass.  Host input goes through two device blocks:
 // the copy of one (on a copy stream owned by the state) overlaps the work on
-// the other (on the caller's stream), ordered by events.
+// the other (on the caller's stream), ordered by events; pinned input of a
+// state without projection is read in place by the leaf kernels instead.
 #include <string.h>
 
 #include <algorithm>
@@ -197,6 +198,23 @@ int push_host_impl(tsnmf_onepass_s* p, const void* X, int64_t rows, int64_t ld, 
             if (e != hipSuccess) return e == hipErrorOutOfMemory ? TSNMF_ERR_NOMEM : hip_fail(e);
         }
     const bool pinned = host_pinned(X);
+    // Pinned input without a projection: the leaf kernels read the blocks
+    // over the host link directly (each element once), no copy at all.
+    void* mapped = nullptr;
+    if (pinned && p->k == 0) {
+        if (hipHostGetDevicePointer(&mapped, const_cast<void*>(X), 0) != hipSuccess) {
+            (void)hipGetLastError();
+            mapped = nullptr;
+        }
+    }
+    if (mapped != nullptr) {
+        for (int64_t r0 = 0; r0 < rows; r0 += br) {
+            const int64_t nb = std::min(br, rows - r0);
+            if (int st = process_block(p, (const char*)mapped + (size_t)r0 * ld * p->elem, nb, ld, stream)) return st;
+        }
+        TSNMF_HIP(hipStreamSynchronize(stream));     // the kernels read X: done before X may be reused
+        return TSNMF_OK;
+    }
     if (!pinned)
         for (int b = 0; b < 2; ++b)
             if (p->pin[b] == nullptr) {
@@ -210,7 +228,9 @@ int push_host_impl(tsnmf_onepass_s* p, const void* X, int64_t rows, int64_t ld, 
         const char* src = (const char*)X + (size_t)r0 * ld * p->elem;
         // device block b is free once the work on its previous contents is done
         TSNMF_HIP(hipStreamWaitEvent(p->copy, p->used[b], 0));
-        if (pinned) {
+        if (pinned && (size_t)ld * p->elem == rowbytes) {
+            TSNMF_HIP(hipMemcpyAsync(p->dev[b], src, (size_t)nb * rowbytes, hipMemcpyHostToDevice, p->copy));
+        } else if (pinned) {
             TSNMF_HIP(hipMemcpy2DAsync(p->dev[b], rowbytes, src, (size_t)ld * p->elem, rowbytes, (size_t)nb,
                                        hipMemcpyHostToDevice, p->copy));
         } else {

@@ -154,64 +154,69 @@ template <typename T, typename TI, int N, int RPL> struct Small {
             const TR DR = (TR)D;
             const TR sigma = lane_bcast(DR, 0);
             const TR alpha = lane_bcast(rj, 0);
+            // sigma is wave-uniform (a lane broadcast): a column already zero
+            // below the diagonal of this block (sigma = 0) leaves R and the
+            // block unchanged, so the whole step is skipped by a scalar branch
+            // and the common path carries no selects.  Otherwise alpha^2 +
+            // sigma > 0 and beta is nonzero.
             const bool live = sigma != TR(0);
-            TR beta, inv_beta, s;
-            if constexpr (sizeof(T) == 4) {
-                // FP32 block: sigma is a nonzero FP32 value when live, so
-                // alpha^2 + sigma and beta (alpha - beta) lie far inside the
-                // normal FP64 range, and one reciprocal serves both scalars.
-                const TR nrm = sqrt_normal(fma_t(alpha, alpha, sigma));
-                beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
-                const TR amb = alpha - beta;
-                const TR q = rcp_fast<TR>(beta * amb);                      // unused unless live
-                inv_beta = amb * q;
-                s = live ? beta * q : TR(0);                                // 1 / (alpha - beta)
-            } else {
-                const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
-                beta = live ? (alpha >= TR(0) ? -nrm : nrm) : alpha;
-                inv_beta = rcp_fast<TR>(beta);
-                s = live ? rcp_fast<TR>(alpha - beta) : TR(0);
-            }
-            const TR tau = live ? (beta - alpha) * inv_beta : TR(0);
-            const T c = live ? (T)inv_beta : T(0);                        // = -tau * s
-            const TR w = fma_t(s, DR, rj);
-            TR rn = fma_t(-tau, w, rj);
-            if (vi == 0) rn = beta;
-            row[vi] = rn;
-            const T wt = (T)w;
-            if constexpr (LB) {
-                wb[vi] = wt;                         // lanes sharing vi store the same value
-                wave_lds_sync();
-            }
-            T t[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) t[r] = c * x[r][J];
-            if constexpr (!LB) {
-#pragma unroll
-                for (int v = 1; v < CNT; ++v) {
-                    const T wk = lane_bcast(wt, bfly_lane(v, P));
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wk, x[r][J + v]);
+            if (live) {
+                TR beta, inv_beta, s;
+                if constexpr (sizeof(T) == 4) {
+                    // FP32 block: sigma is a nonzero FP32 value, so alpha^2 +
+                    // sigma and beta (alpha - beta) lie far inside the normal
+                    // FP64 range, and one reciprocal serves both scalars.
+                    const TR nrm = sqrt_normal(fma_t(alpha, alpha, sigma));
+                    beta = alpha >= TR(0) ? -nrm : nrm;
+                    const TR amb = alpha - beta;
+                    const TR q = rcp_fast<TR>(beta * amb);
+                    inv_beta = amb * q;
+                    s = beta * q;                                            // 1 / (alpha - beta)
+                } else {
+                    const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
+                    beta = alpha >= TR(0) ? -nrm : nrm;
+                    inv_beta = rcp_fast<TR>(beta);
+                    s = rcp_fast<TR>(alpha - beta);
                 }
-            } else {
-                const T* wr = (const T*)__builtin_assume_aligned(wb, 16);
-                constexpr int E = 16 / (int)sizeof(T);   // values per 16-byte read
+                const TR tau = (beta - alpha) * inv_beta;
+                const TR w = fma_t(s, DR, rj);
+                TR rn = fma_t(-tau, w, rj);
+                if (vi == 0) rn = beta;
+                row[vi] = rn;
+                // the block update B(:, k) += (1 / beta) B(:, j) w_k takes
+                // w_k / beta, formed once per value instead of scaling B(:, j)
+                const T wt = (T)(w * inv_beta);
+                if constexpr (LB) {
+                    wb[vi] = wt;                     // lanes sharing vi store the same value
+                    wave_lds_sync();
+                }
+                if constexpr (!LB) {
 #pragma unroll
-                for (int q = 0; q < (CNT + E - 1) / E; ++q) {
-                    T wq[E];
-                    if constexpr (E == 4) {
-                        const float4 f = ((const float4*)wr)[q];
-                        wq[0] = f.x; wq[1] = f.y; wq[2] = f.z; wq[3] = f.w;
-                    } else {
-                        const double2 f = ((const double2*)wr)[q];
-                        wq[0] = f.x; wq[1] = f.y;
+                    for (int v = 1; v < CNT; ++v) {
+                        const T wk = lane_bcast(wt, bfly_lane(v, P));
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(x[r][J], wk, x[r][J + v]);
                     }
+                } else {
+                    const T* wr = (const T*)__builtin_assume_aligned(wb, 16);
+                    constexpr int E = 16 / (int)sizeof(T);   // values per 16-byte read
 #pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const int v = q * E + e;
-                        if (v >= 1 && v < CNT) {
+                    for (int q = 0; q < (CNT + E - 1) / E; ++q) {
+                        T wq[E];
+                        if constexpr (E == 4) {
+                            const float4 f = ((const float4*)wr)[q];
+                            wq[0] = f.x; wq[1] = f.y; wq[2] = f.z; wq[3] = f.w;
+                        } else {
+                            const double2 f = ((const double2*)wr)[q];
+                            wq[0] = f.x; wq[1] = f.y;
+                        }
 #pragma unroll
-                            for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(t[r], wq[e], x[r][J + v]);
+                        for (int e = 0; e < E; ++e) {
+                            const int v = q * E + e;
+                            if (v >= 1 && v < CNT) {
+#pragma unroll
+                                for (int r = 0; r < RPL; ++r) x[r][J + v] = fma_t(x[r][J], wq[e], x[r][J + v]);
+                            }
                         }
                     }
                 }

@@ -182,3 +182,25 @@ def test_argument_errors(lib):
     Xh = np.zeros((10, 8))
     assert lib.tsnmf_onepass_push_host(col.h, Xh, 10, 8) == 4      # TSNMF_ERR_UNSUPPORTED
     assert lib.tsnmf_onepass_result(op.h, R) == 0
+
+
+def test_single_column_and_blocks_shorter_than_n(lib):
+    """n = 1 (R is the column's 2-norm), and 40 columns pushed in blocks of
+    fewer rows than columns."""
+    x = synth.random_matrix(1_001, 1, dtype=torch.float64, seed_tag=47).cuda()
+    op = lib.OnePass(1, dtype=torch.float64)
+    for a, b in _bounds(1_001, [1, 500]):
+        op.push(x[a:b])
+    R, cs, _ = op.result()
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    assert abs(R.item() - np.linalg.norm(xh)) <= 1e-14 * np.linalg.norm(xh)
+    assert abs(cs.item() - np.abs(xh).sum()) <= 1e-13 * np.abs(xh).sum()
+    m, n = 200, 40
+    X = synth.random_matrix(m, n, dtype=torch.float64, seed_tag=48, dist="lognormal")
+    op = lib.OnePass(n, dtype=torch.float64)
+    for a in range(0, m, 13):                    # 13-row blocks, 40 columns
+        op.push(X[a:a + 13].cuda())
+    R, cs, _ = op.result()
+    torch.cuda.synchronize()
+    _check_against_oracle(_np(R), _np(cs), X.numpy(), 1e-12, 1e-10, 1e-13, norm_tol=1e-12)

@@ -129,3 +129,37 @@ def test_argument_errors(lib):
     assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 5, K, R, 4, S, info) == -6
     assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 4, K, R, 3, S, info) == -9
     assert lib.tsnmf_rank_sweep(R, 4, 4, 4, None, 4, K, R, 4, S, None) == -11
+
+
+def test_rsvd_rank_deficient(lib):
+    """R of a matrix with a zero column and a repeated column: exact zero
+    singular values, zero U columns for them, V still orthonormal."""
+    rng = np.random.default_rng([72])
+    A = rng.uniform(size=(500, 6))
+    X = np.concatenate([A, np.zeros((500, 1)), A[:, :1]], axis=1)      # rank 6 of 8
+    R = otsqr.tsqr_r_final(X, leaf_rows=500)
+    S, U, V, info = lib.rsvd(_cuda(R))
+    torch.cuda.synchronize()
+    so = np.linalg.svd(R, compute_uv=False)
+    Sg, Ug, Vg = S.cpu().numpy(), U.cpu().numpy(), V.cpu().numpy()
+    assert np.all(np.abs(Sg - so) <= 1e-13 * so[0] + 1e-12 * so)
+    assert np.all(Sg[6:] <= 1e-13 * Sg[0])
+    assert np.abs(Vg.T @ Vg - np.eye(8)).max() <= 1e-12
+    assert np.abs(Ug @ np.diag(Sg) @ Vg.T - R).max() <= 1e-12 * so[0]
+
+
+def test_rank_sweep_stops_when_the_residual_vanishes(lib):
+    """M = [e1 e2 e3 e1 e2]: after three picks the residual is exactly zero,
+    so SPA stops (info = 3), K holds -1 past its picks and the residuals past
+    them are NaN; the first three are zero after the third pick."""
+    M = np.zeros((3, 5))
+    M[0, 0] = M[1, 1] = M[2, 2] = 1.0
+    M[0, 3] = M[1, 4] = 1.0
+    K, res, _, info = lib.rank_sweep(_cuda(M), 5)
+    torch.cuda.synchronize()
+    Ko, reso = orsvd.rank_sweep(M, 5)
+    assert int(info.item()) == 3 == len(Ko)
+    assert K.cpu().tolist()[:3] == Ko and K.cpu().tolist()[3:] == [-1, -1]
+    r = res.cpu().numpy()
+    assert np.allclose(r[:3], reso, rtol=0, atol=1e-15) and r[2] <= 1e-30
+    assert np.all(np.isnan(r[3:]))

@@ -239,6 +239,8 @@ def extras(torch, tsnmf, synth, dev, check=True, tuned=None):
         "gram_rel_max": max(errs) if errs else None, "gram_tol": 1e-6,
         "max_rel_diff_vs_fp64_baseline": max(agree) if agree else None,
         "graph_captured": True,
+        "geometry": ({"source": "tuned.txt", "slab_shift": list(tuned[("batch",)][0]), "note": tuned[("batch",)][1]}
+                     if tuned and ("batch",) in tuned else {"source": "library default"}),
     }
     del mats, b, g, Rs, css, res
     torch.cuda.empty_cache()

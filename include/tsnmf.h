@@ -212,6 +212,25 @@ int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, 
                          const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
                          hipStream_t stream);
 
+/*
+ * tsnmf_tsqr_r_batched_ex: tsnmf_tsqr_r_batched with an explicit slab height
+ * per width class.  The classes are 0: n = 16 with ld = 16, 1: n = 32 with
+ * ld = 32 (one wave per slab), 2: other n <= 64, 3: n <= 128; a class's slab
+ * is its default height times 2^slab_shift[c] (0..8; longer slabs mean fewer
+ * tree leaves and fewer, longer work items).  cfg = NULL is the library
+ * default, or the "batch" line of the loaded autotune table, which
+ * tsnmf_tsqr_r_batched applies too.  Only the work split changes, so R
+ * equals the default's up to rounding.  reserved must be 0.
+ * Returns as tsnmf_tsqr_r_batched, and -8 for an invalid cfg.
+ */
+typedef struct tsnmf_batch_config {
+    int32_t slab_shift[4];
+    int32_t reserved[4];
+} tsnmf_batch_config;
+int tsnmf_tsqr_r_batched_ex(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
+                            const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
+                            const tsnmf_batch_config* cfg, hipStream_t stream);
+
 /* Reserve the batched workspace for up to `max_batch` matrices with at most
    `max_rows` rows in total, at the default slab heights for any widths, so
    that tsnmf_tsqr_r_batched can be captured into a graph.  Host call,

@@ -215,7 +215,28 @@ int tsnmf_tsqr_r_batched(int32_t batch, const void* const* X, const int64_t* m, 
     if (ld == nullptr) return -5;
     if (flags != TSNMF_F32) return -6;
     if (R == nullptr) return -7;
-    return tsqr_batched_impl(batch, X, m, n, ld, R, colsum, stream);
+    return tsqr_batched_impl(batch, X, m, n, ld, R, colsum, tune_batch_shift(), stream);
+}
+
+int tsnmf_tsqr_r_batched_ex(int32_t batch, const void* const* X, const int64_t* m, const int64_t* n,
+                            const int64_t* ld, uint32_t flags, double* const* R, double* const* colsum,
+                            const tsnmf_batch_config* cfg, hipStream_t stream) {
+    if (batch < 1 || batch > TSNMF_MAX_BATCH) return -1;
+    if (X == nullptr) return -2;
+    if (m == nullptr) return -3;
+    if (n == nullptr) return -4;
+    if (ld == nullptr) return -5;
+    if (flags != TSNMF_F32) return -6;
+    if (R == nullptr) return -7;
+    int cshift = tune_batch_shift();
+    if (cfg != nullptr) {
+        cshift = 0;
+        for (int c = 0; c < 4; ++c) {
+            if (cfg->slab_shift[c] < 0 || cfg->slab_shift[c] > 8 || cfg->reserved[c] != 0) return -8;
+            cshift |= cfg->slab_shift[c] << (8 * c);
+        }
+    }
+    return tsqr_batched_impl(batch, X, m, n, ld, R, colsum, cshift, stream);
 }
 
 int tsnmf_reserve_batched(int32_t max_batch, int64_t max_rows) {

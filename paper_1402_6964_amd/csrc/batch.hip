@@ -162,7 +162,10 @@ template <typename V> __device__ V block_exclusive_scan(V v, V* tmp, V* total) {
 __global__ void __launch_bounds__(kPlanThreads)
 batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* n, const int64_t* ld,
                   double* const* R, double* const* colsum, BatchHdr* hdr, BatchMat* mats, int64_t* iprefix,
-                  int* tickets, int64_t tcap, double* words, int64_t dcap) {
+                  int* tickets, int64_t tcap, double* words, int64_t dcap, int cshift) {
+    // per-class slab doubling of the configuration (8 bits per class), on top
+    // of the doubling the workspace may force
+    auto cls_shift = [cshift](int c) { return (cshift >> (8 * c)) & 0xff; };
     __shared__ float cost[kMaxBatch];
     __shared__ int order[kMaxBatch];
     __shared__ int64_t tmp[kPlanThreads];
@@ -204,7 +207,7 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
         for (int p = p0; p < p1; ++p) {
             const int i = order[p];
             if (cost[i] < 0.0f) continue;
-            const Sizes s = matrix_sizes(m[i], n[i], class_of(n[i], ld[i]), shift);
+            const Sizes s = matrix_sizes(m[i], n[i], class_of(n[i], ld[i]), shift + cls_shift(class_of(n[i], ld[i])));
             w += s.words;
             k += s.tickets;
         }
@@ -238,7 +241,7 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
     for (int p = p0; p < p1; ++p) {
         const int i = order[p];
         if (cost[i] < 0.0f) continue;
-        const Sizes s = matrix_sizes(m[i], n[i], class_of(n[i], ld[i]), shift);
+        const Sizes s = matrix_sizes(m[i], n[i], class_of(n[i], ld[i]), shift + cls_shift(class_of(n[i], ld[i])));
         it += s.items;
         w += s.words;
         k += s.tickets;
@@ -253,7 +256,7 @@ batch_plan_kernel(int B, const void* const* X, const int64_t* m, const int64_t* 
         iprefix[p] = ito;
         if (cost[i] >= 0.0f) {
             const int c = class_of(n[i], ld[i]);
-            const Sizes s = matrix_sizes(m[i], n[i], c, shift);
+            const Sizes s = matrix_sizes(m[i], n[i], c, shift + cls_shift(c));
             d.X = X[i];
             d.m = m[i];
             d.ld = ld[i];
@@ -461,7 +464,7 @@ int batch_reserve(int32_t max_batch, int64_t max_rows) {
 }
 
 int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const int64_t* n, const int64_t* ld,
-                      double* const* R, double* const* colsum, hipStream_t stream) {
+                      double* const* R, double* const* colsum, int cshift, hipStream_t stream) {
     int dev = 0;
     TSNMF_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_bws_mu);
@@ -512,7 +515,7 @@ int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const i
     if (prof_all)
         if (int st = profile_event(stream, &p0)) return st;
     hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, (int)B, X, m, n, ld, R, colsum,
-                       hdr, mats, iprefix, tk, tcap, wd, dcap);
+                       hdr, mats, iprefix, tk, tcap, wd, dcap, cshift);
     TSNMF_LAUNCH_CHECK();
     if (prof_all) {
         if (int st = profile_event(stream, &p1)) return st;

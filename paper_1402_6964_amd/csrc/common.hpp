@@ -52,6 +52,9 @@ bool profile_take_split(hipEvent_t* end0, hipEvent_t* begin1);
 
 // Entry of the loaded autotune table for this call, if any.
 bool tune_lookup(uint32_t flags, int64_t m, int n, int64_t ld, tsnmf_tsqr_config* out);
+// Per-class slab shifts of the batched call from the loaded table (8 bits per
+// class), 0 when the table has no "batch" line.
+int tune_batch_shift();
 
 // Implementations behind the C entry points (arguments already validated).
 int select_spa_impl(const double* M, int p, int n, int ldm, const double* colscale, int r, int* K, double* score,
@@ -72,7 +75,7 @@ int rank_sweep_impl(const double* R, int p, int n, int ldr, const double* colsca
                     int ldh, double* resid, int* info, hipStream_t stream);
 int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float* out, hipStream_t stream);
 int tsqr_batched_impl(int32_t B, const void* const* X, const int64_t* m, const int64_t* n, const int64_t* ld,
-                      double* const* R, double* const* colsum, hipStream_t stream);
+                      double* const* R, double* const* colsum, int cshift, hipStream_t stream);
 int batch_reserve(int32_t max_batch, int64_t max_rows);
 int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, double* R,
                 double* colsum, const tsnmf_tsqr_config* cfg, hipStream_t stream, void* fixed_ws = nullptr,

@@ -5,9 +5,11 @@
 // matches each call.  A line
 //     tsqr <f32|f64> <row|col> <leaf f32|f64> <ld == n: 1|0> <n> <floor(log2 m)> <leaf_rows> <tree_arity> [<wy_panel>]
 // keys an entry by input dtype, layout, row-block precision, whether rows are
-// contiguous, width and row-count bucket; '#' starts a comment.  Every entry
-// changes only the launch geometry, so the result equals the default's up to
-// rounding.
+// contiguous, width and row-count bucket; a line
+//     batch <shift class 0> <shift class 1> <shift class 2> <shift class 3>
+// gives the slab doubling per width class of the batched call; '#' starts a
+// comment.  Every entry changes only the launch geometry, so the result
+// equals the default's up to rounding.
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -23,6 +25,7 @@ namespace {
 using Key = std::tuple<int, int, int, int, int, int>;   // dtype, col, leaf64, ldeq, n, log2 m
 std::mutex g_tune_mu;
 std::map<Key, tsnmf_tsqr_config> g_tune;
+int g_batch_shift = 0;
 
 int floor_log2(int64_t m) {
     int r = 0;
@@ -43,6 +46,11 @@ Key key_of(uint32_t flags, int64_t m, int n, int64_t ld) {
 
 }  // namespace
 
+int tune_batch_shift() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_batch_shift;
+}
+
 bool tune_lookup(uint32_t flags, int64_t m, int n, int64_t ld, tsnmf_tsqr_config* out) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (g_tune.empty()) return false;
@@ -60,16 +68,33 @@ extern "C" int tsnmf_tune_load(const char* path) {
     if (path == nullptr) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune.clear();
+        g_batch_shift = 0;
         return TSNMF_OK;
     }
     FILE* f = std::fopen(path, "r");
     if (f == nullptr) return -1;
     std::map<Key, tsnmf_tsqr_config> table;
+    int batch_shift = 0;
     char line[512];
     bool ok = true;
     while (std::fgets(line, sizeof line, f) != nullptr) {
         char* hash = std::strchr(line, '#');
         if (hash != nullptr) *hash = '\0';
+        int bs[4];
+        char bkind[16];
+        if (std::sscanf(line, "%15s", bkind) == 1 && !std::strcmp(bkind, "batch")) {
+            if (std::sscanf(line, "%15s %d %d %d %d", bkind, &bs[0], &bs[1], &bs[2], &bs[3]) != 5) {
+                ok = false;
+                break;
+            }
+            batch_shift = 0;
+            for (int c = 0; c < 4; ++c) {
+                if (bs[c] < 0 || bs[c] > 8) ok = false;
+                batch_shift |= (bs[c] & 0xff) << (8 * c);
+            }
+            if (!ok) break;
+            continue;
+        }
         char kind[16], dt[8], lay[8], leaf[8];
         int ldeq = 0, n = 0, lg = 0, arity = 0, wy = 0;
         long long leaf_rows = 0;
@@ -97,5 +122,6 @@ extern "C" int tsnmf_tune_load(const char* path) {
     if (!ok) return -1;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune.swap(table);
+    g_batch_shift = batch_shift;
     return TSNMF_OK;
 }

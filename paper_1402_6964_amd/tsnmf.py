@@ -40,6 +40,18 @@ _u32 = ctypes.c_uint32
 _u64 = ctypes.c_uint64
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("slab_shift", _i32 * 4), ("reserved", _i32 * 4)]
+
+
+def batch_config(shifts):
+    """BatchConfig from four per-class slab shifts (16, 32, <= 64, <= 128)."""
+    c = BatchConfig()
+    for i, v in enumerate(shifts):
+        c.slab_shift[i] = int(v)
+    return c
+
+
 class TsqrConfig(ctypes.Structure):
     _fields_ = [("leaf_rows", _i64), ("tree_arity", _i32), ("rows_per_lane", _i32), ("wy_panel", _i32),
                 ("reserved", _i32)]
@@ -71,6 +83,8 @@ _tsqr_r_ex = _sig("tsnmf_tsqr_r_ex", ctypes.c_int,
                   [_vp, _i64, _i64, _i64, _u32, _vp, _vp, ctypes.POINTER(TsqrConfig), _vp])
 _tsqr_r_kron = _sig("tsnmf_tsqr_r_kron", ctypes.c_int, [_vp, _i64, _i32, _i64, _vp, _vp, _vp])
 _tsqr_batched = _sig("tsnmf_tsqr_r_batched", ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp])
+_tsqr_batched_ex = _sig("tsnmf_tsqr_r_batched_ex", ctypes.c_int,
+                        [_i32, _vp, _vp, _vp, _vp, _u32, _vp, _vp, ctypes.POINTER(BatchConfig), _vp])
 _reserve_batched = _sig("tsnmf_reserve_batched", ctypes.c_int, [_i32, _i64])
 _gauss_proj = _sig("tsnmf_gauss_proj", ctypes.c_int,
                    [_vp, _i64, _i64, _i64, _u32, _i32, _u64, _i64, _vp, _vp, _vp])
@@ -154,6 +168,12 @@ def tsnmf_tsqr_r_ex(X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):
 
 def tsnmf_tsqr_r_kron(A, p, q, lda, R, colsum=None, stream=None):
     return _tsqr_r_kron(_ptr(A), p, q, lda, _ptr(R), _ptr(colsum), _stream(stream))
+
+
+def tsnmf_tsqr_r_batched_ex(batch, X, m, n, ld, flags, R, colsum=None, cfg=None, stream=None):
+    c = None if cfg is None else ctypes.byref(cfg)
+    return _tsqr_batched_ex(batch, _ptr(X), _ptr(m), _ptr(n), _ptr(ld), flags, _ptr(R), _ptr(colsum), c,
+                            _stream(stream))
 
 
 def tsnmf_tsqr_r_batched(batch, X, m, n, ld, flags, R, colsum=None, stream=None):
@@ -543,10 +563,16 @@ class Batch:
         self.R = arr([r.data_ptr() for r in self.Rbuf])
         self.colsum = arr([c.data_ptr() for c in self.cs]) if with_colsum else None
 
-    def run(self, stream=None):
-        _check("tsnmf_tsqr_r_batched",
-               tsnmf_tsqr_r_batched(len(self.mats), self.X, self.m, self.n, self.ld, F32, self.R, self.colsum,
-                                    stream))
+    def run(self, stream=None, config=None):
+        """config: None (library default or the loaded table) or a BatchConfig."""
+        if config is None:
+            _check("tsnmf_tsqr_r_batched",
+                   tsnmf_tsqr_r_batched(len(self.mats), self.X, self.m, self.n, self.ld, F32, self.R, self.colsum,
+                                        stream))
+        else:
+            _check("tsnmf_tsqr_r_batched_ex",
+                   tsnmf_tsqr_r_batched_ex(len(self.mats), self.X, self.m, self.n, self.ld, F32, self.R,
+                                           self.colsum, config, stream))
 
     def results(self):
         """[(R, colsum)] with R the logical n x n view of each output."""
@@ -554,10 +580,10 @@ class Batch:
                 for r, c in zip(self.Rbuf, self.cs or [None] * len(self.Rbuf))]
 
 
-def tsqr_r_batched(mats, with_colsum=True, stream=None):
+def tsqr_r_batched(mats, with_colsum=True, stream=None, config=None):
     """R factors and column sums of a list of row-major FP32 CUDA matrices."""
     b = Batch(mats, with_colsum)
-    b.run(stream)
+    b.run(stream, config)
     return b.results()
 
 

@@ -1,6 +1,7 @@
 """Autotuner for the TSQR launch geometry (leaf height and tree arity).
 
     python -m paper_1402_6964_amd.tune --m 10000000 --n 25 [--dtype f32] [--layout row] [--leaf f32] [--pad 0]
+    python -m paper_1402_6964_amd.tune --batched
 
 For one input shape it times tsnmf_tsqr_r_ex over a grid of leaf heights
 (rows per slab, the TSQR leaf) and, for n <= 32, tree group sizes (slab
@@ -17,6 +18,14 @@ X explicitly.
 The row-block height (rows one wave holds in registers per Householder pass)
 is a compile-time constant per width, chosen by measurement; the tunable
 "leaf height" of the TSQR is the slab, which is a runtime parameter.
+
+--batched tunes the batched call on the 512-matrix workload: the slab height
+of each width class (16 and 32 columns, one wave per slab; up to 64; up to
+128) as a power-of-two multiple of its default, one class at a time (each
+class keeps the best value found for it while the next is swept).  Every
+configuration's R factors must equal the default's within the rounding bound;
+the best goes into the table's "batch" line, which tsnmf_tune_load makes the
+library apply to every tsnmf_tsqr_r_batched call.
 """
 
 import argparse
@@ -29,7 +38,9 @@ from . import synth, tsnmf
 
 TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.txt")
 HEADER = ("# tsnmf autotune table: tsqr <dtype> <layout> <leaf precision> <ld == n> <n> <floor(log2 m)> "
-          "<leaf_rows> <tree_arity> <wy_panel>\n")
+          "<leaf_rows> <tree_arity> <wy_panel>\n"
+          "#                       batch <slab shift, 16 columns> <32 columns> <up to 64> <up to 128>\n")
+BATCH = ("batch",)
 
 
 def key(dtype, layout, leaf, ldeq, n, m):
@@ -37,13 +48,17 @@ def key(dtype, layout, leaf, ldeq, n, m):
 
 
 def load(path=None):
-    """The table as {key: (leaf_rows, tree_arity, wy_panel, comment)}."""
+    """The table as {key: (leaf_rows, tree_arity, wy_panel, comment)}, and the
+    batched call's slab shifts as {BATCH: (shifts, comment)}."""
     out = {}
     try:
         with open(path or TUNED) as f:
             for line in f:
                 body, _, note = line.partition("#")
                 p = body.split()
+                if len(p) == 5 and p[0] == "batch":
+                    out[BATCH] = (tuple(int(v) for v in p[1:]), note.strip())
+                    continue
                 if len(p) not in (9, 10) or p[0] != "tsqr":
                     continue
                 k = (p[1], p[2], p[3], int(p[4]), int(p[5]), int(p[6]))
@@ -56,7 +71,10 @@ def load(path=None):
 def save(table, path=None):
     with open(path or TUNED, "w") as f:
         f.write(HEADER)
-        for k in sorted(table):
+        if BATCH in table:
+            shifts, note = table[BATCH]
+            f.write("batch " + " ".join(str(int(v)) for v in shifts) + (f"  # {note}" if note else "") + "\n")
+        for k in sorted(k for k in table if k != BATCH):
             leaf_rows, arity, wy, note = table[k]
             f.write(f"tsqr {k[0]} {k[1]} {k[2]} {k[3]} {k[4]} {k[5]} {leaf_rows} {arity} {wy}"
                     + (f"  # {note}" if note else "") + "\n")
@@ -133,8 +151,42 @@ def tune(X, leaf_f64=False, grid=None, arity_grid=None, wy_grid=None, verbose=Tr
     return key_of(X, leaf_f64), (best[1], best[2], best[3], note), results
 
 
+def time_batch(b, cfg, reps=5):
+    b.run(config=cfg)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.run(config=cfg)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps, [r.clone() for r, _ in b.results()]
+
+
+def tune_batched(b, verbose=True, grid=(0, 1, 2, 3)):
+    """Per-class slab shifts of the batched call, one class at a time."""
+    best = [0, 0, 0, 0]
+    t0, R0 = time_batch(b, tsnmf.batch_config(best))
+    tbest = t0
+    for c in range(4):
+        for v in grid:
+            if v == best[c]:
+                continue
+            cand = list(best)
+            cand[c] = v
+            ms, R = time_batch(b, tsnmf.batch_config(cand))
+            err = max(float((r - r0).abs().max() / r0.abs().max().clamp_min(1e-300)) for r, r0 in zip(R, R0))
+            ok = err <= 1e-5
+            if verbose:
+                print(f"shifts {cand}  {ms:8.3f} ms  err {err:.1e}{'' if ok else '  REJECTED'}", flush=True)
+            if ok and ms < tbest:
+                tbest, best = ms, cand
+    return tuple(best), f"{tbest:.3f} ms against {t0:.3f} ms default"
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--batched", action="store_true", help="tune the batched call on the 512-matrix workload")
     ap.add_argument("--m", type=int, default=10_000_000)
     ap.add_argument("--n", type=int, default=25)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
@@ -143,6 +195,17 @@ def main():
     ap.add_argument("--pad", type=int, default=0, help="extra elements of the row stride (row-major)")
     ap.add_argument("--no-save", action="store_true")
     args = ap.parse_args()
+    if args.batched:
+        shapes = synth.batch_shapes()
+        mats = [synth.batch_matrix(q, m, n, device="cuda")["X"] for q, (m, n) in enumerate(shapes)]
+        b = tsnmf.Batch(mats)
+        shifts, note = tune_batched(b)
+        print("batch", shifts, note)
+        if not args.no_save:
+            table = load()
+            table[BATCH] = (shifts, note)
+            save(table)
+        return
     dt = torch.float32 if args.dtype == "f32" else torch.float64
     if args.layout == "row":
         X = synth.random_matrix(args.m, args.n + args.pad, device="cuda", dtype=dt, seed_tag=11)[:, :args.n]

@@ -84,6 +84,21 @@ def test_mixed_batch_matches_oracle(lib):
         _check(R.cpu().numpy(), cs.cpu().numpy(), X, elem_tol=None if m < n else 2e-5, name=f"{m}x{n}")
 
 
+@pytest.mark.parametrize("shifts", [(1, 2, 1, 2), (3, 3, 3, 3), (8, 0, 8, 0)])
+def test_slab_shifts_match_oracle(lib, shifts):
+    """tsnmf_tsqr_r_batched_ex with longer slabs per width class (fewer
+    leaves and tree levels, down to one slab per matrix at shift 8): the same
+    bars as the default geometry."""
+    mats = _mixed(seed_tag=60)
+    dv = _device_views(mats)
+    b = lib.Batch(dv)
+    b.run(config=lib.batch_config(shifts))
+    torch.cuda.synchronize()
+    for (m, n, extra), full, (R, cs) in zip(MIXED, mats, b.results()):
+        X = full[:, :n].numpy()
+        _check(R.cpu().numpy(), cs.cpu().numpy(), X, elem_tol=None if m < n else 2e-5, name=f"{shifts} {m}x{n}")
+
+
 def test_batch_equals_single_calls(lib):
     """The same matrices through tsnmf_tsqr_r one by one: R agrees to FP32
     rounding (the slab heights and tree shapes differ)."""
@@ -203,6 +218,12 @@ def test_argument_errors(lib):
     assert lib.tsnmf_tsqr_r_batched(2, a, a, a, a, lib.F64, a) == -6
     assert lib.tsnmf_tsqr_r_batched(2, a, a, a, a, lib.F32 | lib.COL_MAJOR, a) == -6
     assert lib.tsnmf_tsqr_r_batched(2, a, a, a, a, lib.F32, None) == -7
+    for bad in ((9, 0, 0, 0), (0, -1, 0, 0)):
+        assert lib.tsnmf_tsqr_r_batched_ex(2, a, a, a, a, lib.F32, a, None, lib.batch_config(bad)) == -8
+    cfg = lib.batch_config((0, 0, 0, 0))
+    cfg.reserved[2] = 1
+    assert lib.tsnmf_tsqr_r_batched_ex(2, a, a, a, a, lib.F32, a, None, cfg) == -8
+    assert lib.tsnmf_tsqr_r_batched_ex(2, a, a, a, a, lib.F32, None, None, cfg) == -7
     assert lib.tsnmf_reserve_batched(0, 10) == -1
     assert lib.tsnmf_reserve_batched(4, -1) == -2
 

@@ -27,9 +27,11 @@ def test_save_and_load_round_trip(tune):
     t = {("f32", "row", "f32", 1, 25, 23): (4883, 16, 0, "0.40 ms"),
          ("f32", "row", "f64", 0, 25, 23): (1000, 0, 0, ""),
          ("f32", "col", "f32", 1, 64, 25): (0, 0, 16, "")}
+    t[tune.BATCH] = ((0, 1, 2, 1), "70 ms")
     tune.save(t)
     assert tune.load() == t
     txt = open(tune.TUNED).read()
+    assert "batch 0 1 2 1" in txt
     assert "tsqr f32 row f32 1 25 23 4883 16 0" in txt and "tsqr f32 row f64 0 25 23 1000 0 0" in txt
     assert "tsqr f32 col f32 1 64 25 0 0 16" in txt
 
@@ -60,7 +62,7 @@ def test_library_parser_accepts_the_table_and_rejects_bad_lines(tmp_path):
     so = _lib()
     good = tmp_path / "good.txt"
     good.write_text("# comment\n\ntsqr f32 row f32 1 25 23 4883 16  # 0.40 ms\ntsqr f64 col f64 0 64 20 0 0\n"
-                    "tsqr f32 col f32 1 64 25 0 0 16\n")
+                    "tsqr f32 col f32 1 64 25 0 0 16\nbatch 0 1 2 1  # 68 ms\n")
     assert so.tsnmf_tune_load(str(good).encode()) == 0
     for bad in ("tsqr f32 row f32 1 25 23 4883\n",        # missing field
                 "tsqr f16 row f32 1 25 23 4883 16\n",     # dtype
@@ -68,7 +70,9 @@ def test_library_parser_accepts_the_table_and_rejects_bad_lines(tmp_path):
                 "tsqr f32 row f32 1 500 23 0 0\n",        # width
                 "tsqr f32 row f32 1 25 23 0 1\n",         # arity 1
                 "tsqr f32 col f32 1 64 25 0 0 8\n",       # WY panel width
-                "batch s16 4096\n"):                      # unknown kind
+                "batch s16 4096\n",                       # not four shifts
+                "batch 0 1 2\n",                          # missing shift
+                "batch 0 0 9 0\n"):                       # shift out of range
         p = tmp_path / "bad.txt"
         p.write_text(bad)
         assert so.tsnmf_tune_load(str(p).encode()) == -1, bad

@@ -63,7 +63,15 @@ __device__ __forceinline__ void gauss4(int64_t i, uint32_t q, uint32_t k0, uint3
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two floats rounded to BF16 (nearest even) and packed: a in the low half.
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(floatx2{a, b}, bf16x2));
+}
 
 struct GpArgs {
     const void* X;
@@ -101,8 +109,9 @@ __device__ __forceinline__ float load_f32(const void* X, int64_t idx, bool bf16)
 // one is generated and multiplied, and the staging is double-buffered, so one
 // barrier per chunk orders writes and reads and the loads' latency is hidden
 // behind the generator.
-constexpr int kMfmaRows = 32;
-constexpr int kXsStride = 40;                        // BF16 slots per staged column
+constexpr int kMfmaRows = 32;                       // K of one 16x16x32 BF16 MFMA
+constexpr int kMfmaChunk = 64;                      // rows per barrier: two K steps
+constexpr int kXsStride = 72;                       // BF16 slots per staged column
 
 template <bool BF16_IN>
 __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
@@ -119,6 +128,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
     const int lbase = blockIdx.y * 512 + wv * 64;    // first column l of this wave
     const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
+    const bool want_cs = a.part_cs != nullptr && blockIdx.y == 0;
     floatx4 acc[4][8];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -126,23 +136,23 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
         for (int t = 0; t < 8; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     double csum = 0.0;                               // sums of column col_ld over this thread's rows
     const int col_ld = tid & 127;                    // staging: column handled by this thread
-    const int rgrp = tid >> 7;                       // rows 8 rgrp .. 8 rgrp + 7 of the chunk
+    const int rgrp = tid >> 7;                       // rows 16 rgrp .. 16 rgrp + 15 of the chunk
     const bool stager = col_ld < n;
     // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply per
     // chunk, then one add per row
-    float v[8];
+    float v[16];
     auto load_chunk = [&](int64_t i0) {
-        const int64_t ib = i0 + rgrp * 8;
+        const int64_t ib = i0 + rgrp * 16;
         int64_t idx = ib * a.ld + cb + col_ld;
-        if (stager && ib + 8 <= r1) {                // whole 8-row group: no per-row masks
+        if (stager && ib + 16 <= r1) {               // whole 16-row group: no per-row masks
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 v[t] = load_f32(a.X, idx, BF16_IN);
                 idx += a.ld;
             }
         } else {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < 16; ++t) {
                 v[t] = stager && ib + t < r1 ? load_f32(a.X, idx, BF16_IN) : 0.0f;
                 idx += a.ld;
             }
@@ -150,35 +160,47 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     };
     load_chunk(r0);
     int buf = 0;
-    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaRows, buf ^= 1) {
+    for (int64_t i0 = r0; i0 < r1; i0 += kMfmaChunk, buf ^= 1) {
         if (stager) {
-            bf16x8 pk;
+            if (want_cs) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                csum += (double)__builtin_fabsf(v[t]);
-                pk[t] = (__bf16)v[t];                // round to nearest even
+                for (int t = 0; t < 16; ++t) csum += (double)__builtin_fabsf(v[t]);
             }
-            *(bf16x8*)(xs[buf] + col_ld * kXsStride + rgrp * 8) = pk;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                u32x4 pk;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pk[t] = pack_bf16(v[8 * h + 2 * t], v[8 * h + 2 * t + 1]);
+                *(u32x4*)(xs[buf] + col_ld * kXsStride + rgrp * 16 + 8 * h) = pk;
+            }
         }
-        if (i0 + kMfmaRows < r1) load_chunk(i0 + kMfmaRows);
+        if (i0 + kMfmaChunk < r1) load_chunk(i0 + kMfmaChunk);
         __syncthreads();
         if (lbase < k) {                             // waves past k only stage X
-            bf16x8 av[4];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                float g[4];
-                gauss4(a.row_offset + i0 + 8 * (L >> 4) + t, q, a.key0, a.key1, g);
+            for (int h = 0; h < 2; ++h) {            // K steps: rows i0 + 32 h .. i0 + 32 h + 31
+                u32x4 au[4];                         // A operands: rows t, t + 1 per dword
 #pragma unroll
-                for (int s = 0; s < 4; ++s) av[s][t] = (__bf16)g[s];
-            }
+                for (int t = 0; t < 8; t += 2) {
+                    const int64_t row = a.row_offset + i0 + kMfmaRows * h + 8 * (L >> 4) + t;
+                    float g0[4], g1[4];
+                    gauss4(row, q, a.key0, a.key1, g0);
+                    gauss4(row + 1, q, a.key0, a.key1, g1);
 #pragma unroll
-            for (int nt = 0; nt < 8; ++nt) {
-                if (nt < NT) {
-                    const int c = nt * 16 + (L & 15);
-                    const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + 8 * (L >> 4)) : bf16x8{};
+                    for (int s = 0; s < 4; ++s) au[s][t / 2] = pack_bf16(g0[s], g1[s]);
+                }
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], b, acc[s][nt], 0, 0, 0);
+                for (int nt = 0; nt < 8; ++nt) {
+                    if (nt < NT) {
+                        const int c = nt * 16 + (L & 15);
+                        const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + kMfmaRows * h +
+                                                                  8 * (L >> 4))
+                                               : bf16x8{};
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au[s]),
+                                                                                 b, acc[s][nt], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -395,7 +417,7 @@ int64_t gp_rows_per_wg(int64_t m, int rows_multiple) {
 }  // namespace
 
 int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float* out, hipStream_t stream) {
-    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaChunk);
     const int64_t parts = (m + rpw - 1) / rpw;
     void* ws = nullptr;
     if (int st = workspace_get(kTicketBytes + (size_t)parts * k * 4 + 256, stream, &ws)) return st;
@@ -425,7 +447,7 @@ int gauss_colsum_impl(int64_t m, int k, uint64_t seed, int64_t row_offset, float
 }
 
 size_t gp_workspace_bytes(int64_t m, int n, int k) {
-    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaChunk);
     const int64_t parts = (m + rpw - 1) / rpw;
     return kTicketBytes + (size_t)parts * k * n * 4 + (size_t)parts * n * 8 + 1024;
 }
@@ -434,12 +456,12 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
                     int64_t row_offset, float* Y, double* colsum, hipStream_t stream, double* yacc) {
     const bool bf16 = (flags & TSNMF_DTYPE_MASK) == TSNMF_BF16;
     const bool mfma = bf16 || (flags & TSNMF_GP_MFMA_BF16) != 0;
-    const int rows_multiple = mfma ? kMfmaRows : kSimdRows;
-    const int64_t rpw = gp_rows_per_wg(m, kMfmaRows);
+    // rows per workgroup: a multiple of the matrix-core kernel's 64-row
+    // chunk (and so of the vector kernel's 4 rows) for either path
+    const int64_t rpw = gp_rows_per_wg(m, kMfmaChunk);
     const int64_t parts = (m + rpw - 1) / rpw;
     void* ws = nullptr;
     if (int st = workspace_get(gp_workspace_bytes(m, n, k), stream, &ws)) return st;
-    (void)rows_multiple;
     GpArgs a{};
     a.X = X;
     a.m = m;

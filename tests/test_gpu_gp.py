@@ -13,7 +13,7 @@ itself: projecting an identity block makes every Y entry one G entry, exactly.
 Per-entry bound of Y = G^T X (l, j), FP32 vector path:
     |Y_gpu - Y| <= EPS_G (rho^T |X|) + C_ACC u sqrt(L) (|G|^T |X|) + u |Y|
   with u = 2^-24, L the rows one FP32 accumulator sums (a workgroup takes
-  ceil(m / 2048) rows, rounded up to 32), the workgroup partials added in
+  ceil(m / 2048) rows, rounded up to 64), the workgroup partials added in
   FP64, and C_ACC = 8 on the probabilistic rounding-error bound of a sum of L
   terms (Higham & Mary, SIAM J. Sci. Comput. 2019).
 BF16 matrix-core path, against the oracle on the same BF16-rounded inputs
@@ -76,7 +76,7 @@ def near_bf16_boundary(G):
 
 def acc_rows(m):
     """Rows summed by one FP32 accumulator (upper bound of the launch's)."""
-    return max(32, -(-m // 2048) + 32)
+    return max(64, -(-m // 2048) + 64)
 
 
 def _gp(lib, X, k, seed, mode=None, row_offset=0, colsum=False):

@@ -159,51 +159,71 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
             }
         }
     };
+    // One K step: multiply the A operands `cur` (32 rows from xsb) into acc,
+    // and meanwhile generate the A operands `nxt` of the 32 rows from nrow.
+    // The generator's vector instructions are interleaved with the matrix-core
+    // instructions, so both units work in the same wave.
+    const bool active = lbase < k;                   // waves past k only stage X
+    const int64_t lrow = a.row_offset + 8 * (L >> 4);
+    auto gen_pair = [&](int64_t row, u32x4 (&au)[4], int p) {
+        float g0[4], g1[4];
+        gauss4(row, q, a.key0, a.key1, g0);
+        gauss4(row + 1, q, a.key0, a.key1, g1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) au[s][p] = pack_bf16(g0[s], g1[s]);
+    };
+    auto step = [&](const __bf16* xsb, const u32x4 (&cur)[4], u32x4 (&nxt)[4], int64_t nrow) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            gen_pair(nrow + 2 * p, nxt, p);
+#pragma unroll
+            for (int nt = 2 * p; nt < 2 * p + 2; ++nt) {
+                const bf16x8 b = *(const bf16x8*)(xsb + (nt * 16 + (L & 15)) * kXsStride + 8 * (L >> 4));
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[s]), b,
+                                                                         acc[s][nt], 0, 0, 0);
+            }
+        }
+        // 32 MFMAs, each followed by a share of the generator's instructions;
+        // the B operand of a column tile is read two tiles ahead
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
+            }
+            if (nt < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+    };
+    u32x4 au0[4], au1[4];
+    if (active) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) gen_pair(lrow + r0 + 2 * p, au0, p);
+    }
     load_chunk(r0);
     int buf = 0;
     for (int64_t i0 = r0; i0 < r1; i0 += kMfmaChunk, buf ^= 1) {
-        if (stager) {
-            if (want_cs) {
+        if (want_cs) {
 #pragma unroll
-                for (int t = 0; t < 16; ++t) csum += (double)__builtin_fabsf(v[t]);
-            }
+            for (int t = 0; t < 16; ++t) csum += (double)__builtin_fabsf(v[t]);
+        }
+        // every thread stages its column (zeros past n), so the column tiles
+        // past n multiply zeros
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                u32x4 pk;
+        for (int h = 0; h < 2; ++h) {
+            u32x4 pk;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) pk[t] = pack_bf16(v[8 * h + 2 * t], v[8 * h + 2 * t + 1]);
-                *(u32x4*)(xs[buf] + col_ld * kXsStride + rgrp * 16 + 8 * h) = pk;
-            }
+            for (int t = 0; t < 4; ++t) pk[t] = pack_bf16(v[8 * h + 2 * t], v[8 * h + 2 * t + 1]);
+            *(u32x4*)(xs[buf] + col_ld * kXsStride + rgrp * 16 + 8 * h) = pk;
         }
         if (i0 + kMfmaChunk < r1) load_chunk(i0 + kMfmaChunk);
         __syncthreads();
-        if (lbase < k) {                             // waves past k only stage X
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {            // K steps: rows i0 + 32 h .. i0 + 32 h + 31
-                u32x4 au[4];                         // A operands: rows t, t + 1 per dword
-#pragma unroll
-                for (int t = 0; t < 8; t += 2) {
-                    const int64_t row = a.row_offset + i0 + kMfmaRows * h + 8 * (L >> 4) + t;
-                    float g0[4], g1[4];
-                    gauss4(row, q, a.key0, a.key1, g0);
-                    gauss4(row + 1, q, a.key0, a.key1, g1);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) au[s][t / 2] = pack_bf16(g0[s], g1[s]);
-                }
-#pragma unroll
-                for (int nt = 0; nt < 8; ++nt) {
-                    if (nt < NT) {
-                        const int c = nt * 16 + (L & 15);
-                        const bf16x8 b = c < n ? *(const bf16x8*)(xs[buf] + c * kXsStride + kMfmaRows * h +
-                                                                  8 * (L >> 4))
-                                               : bf16x8{};
-#pragma unroll
-                        for (int s = 0; s < 4; ++s)
-                            acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au[s]),
-                                                                                 b, acc[s][nt], 0, 0, 0);
-                    }
-                }
-            }
+        if (active) {
+            step(xs[buf], au0, au1, lrow + i0 + kMfmaRows);
+            step(xs[buf] + kMfmaRows, au1, au0, lrow + i0 + kMfmaChunk);
         }
     }
     // partial Y: tile (s, nt), element (row rho = 4 (L / 16) + e, column L % 16)

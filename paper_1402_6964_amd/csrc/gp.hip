@@ -98,18 +98,18 @@ __device__ __forceinline__ float load_f32(const void* X, int64_t idx, bool bf16)
 // ---- matrix-core path ------------------------------------------------------------
 //
 // Workgroup = 8 waves; grid.y selects a 512-wide l-range and wave w its
-// 64-wide slice (16 groups q of 4 columns).  Rows are taken 32 at a time (the
-// K of one 16x16x32 BF16 MFMA).  Lane L generates the Philox block of
+// 64-wide slice (16 groups q of 4 columns).  A K step is 32 rows (the K of one
+// 16x16x32 BF16 MFMA).  Lane L generates the Philox block of
 // (row i0 + 8 (L / 16) + t, group q = qbase + (L % 16)) for t = 0..7: its four
 // normals go to four different M-tiles (tile s holds columns 4q + s), so every
-// normal is used once.  The 32 x n chunk of X is staged in LDS as BF16,
-// column by column, so that the B operand of lane L (8 consecutive rows of one
-// column) is one 16-byte read; a column takes 40 BF16 slots (80 bytes), so the
-// 16 lanes of a read phase, and of the staging writes, cover the 64 banks once.
-// The chunk after the current one is loaded into registers while the current
-// one is generated and multiplied, and the staging is double-buffered, so one
-// barrier per chunk orders writes and reads and the loads' latency is hidden
-// behind the generator.
+// normal is used once.  Rows of X come in chunks of 64 (two K steps), staged
+// in LDS as BF16 column by column, so that the B operand of lane L (8
+// consecutive rows of one column) is one 16-byte read; a column takes 72 BF16
+// slots (144 bytes), so the 16 lanes of a read phase cover the 64 banks once.
+// The next chunk is loaded into registers while the current one is generated
+// and multiplied, and the staging is double-buffered, so one barrier per chunk
+// orders writes and reads and the loads' latency is hidden behind the
+// generator.
 constexpr int kMfmaRows = 32;                       // K of one 16x16x32 BF16 MFMA
 constexpr int kMfmaChunk = 64;                      // rows per barrier: two K steps
 constexpr int kXsStride = 72;                       // BF16 slots per staged column
@@ -117,7 +117,7 @@ constexpr int kXsStride = 72;                       // BF16 slots per staged col
 template <bool BF16_IN>
 __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     __shared__ __align__(16) __bf16 xs[2][128 * kXsStride];   // [buffer][column][row]
-    __shared__ double cs_sh[4][128];
+    __shared__ double cs_sh[8][128];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
     // grid.z: block of 128 columns (columns cb .. cb + n - 1 of X and Y)
@@ -135,34 +135,64 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int t = 0; t < 8; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    double csum = 0.0;                               // sums of column col_ld over this thread's rows
-    const int col_ld = tid & 127;                    // staging: column handled by this thread
-    const int rgrp = tid >> 7;                       // rows 16 rgrp .. 16 rgrp + 15 of the chunk
+    // Staging.  FP32 input: thread (column tid % 128, row group tid / 128)
+    // loads 16 rows of one column.  BF16 input: thread (column pair tid % 64,
+    // row group tid / 64) loads 8 rows of two adjacent columns, one dword a
+    // row, and regroups them into two columns of row pairs (the staged form).
+    constexpr int kGroups = BF16_IN ? 8 : 4;         // row groups of the 64-row chunk
+    constexpr int kRows = kMfmaChunk / kGroups;      // rows per thread
+    const int rgrp = BF16_IN ? tid >> 6 : tid >> 7;
+    const int col_ld = BF16_IN ? 2 * (tid & 63) : tid & 127;   // (first) column of this thread
     const bool stager = col_ld < n;
-    // element (i, col_ld) at index i * ld + col_ld: one 64-bit multiply per
-    // chunk, then one add per row
-    float v[16];
+    // both columns of the pair present, and every pair dword-aligned
+    const bool pair_ok = col_ld + 1 < n && (a.ld & 1) == 0 && ((uintptr_t)a.X & 3) == 0;
+    double csum = 0.0, csum1 = 0.0;                  // sums of the thread's column(s) over its rows
+    float v[BF16_IN ? 1 : kRows];
+    uint32_t d[BF16_IN ? kRows : 1];                 // row t: column col_ld low, col_ld + 1 high
     auto load_chunk = [&](int64_t i0) {
-        const int64_t ib = i0 + rgrp * 16;
-        int64_t idx = ib * a.ld + cb + col_ld;
-        if (stager && ib + 16 <= r1) {               // whole 16-row group: no per-row masks
+        const int64_t ib = i0 + rgrp * kRows;
+        int64_t idx = ib * a.ld + cb + col_ld;       // one 64-bit multiply per chunk, one add per row
+        if constexpr (BF16_IN) {
+            const uint16_t* Xh = (const uint16_t*)a.X;
+            if (pair_ok && ib + kRows <= r1) {       // whole row group: no masks
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                v[t] = load_f32(a.X, idx, BF16_IN);
-                idx += a.ld;
+                for (int t = 0; t < kRows; ++t) {
+                    d[t] = *(const uint32_t*)(Xh + idx);
+                    idx += a.ld;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < kRows; ++t) {
+                    const bool in = ib + t < r1;
+                    const uint32_t lo = in && stager ? Xh[idx] : 0u;
+                    const uint32_t hi = in && col_ld + 1 < n ? Xh[idx + 1] : 0u;
+                    d[t] = lo | (hi << 16);
+                    idx += a.ld;
+                }
             }
         } else {
+            if (stager && ib + kRows <= r1) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                v[t] = stager && ib + t < r1 ? load_f32(a.X, idx, BF16_IN) : 0.0f;
-                idx += a.ld;
+                for (int t = 0; t < kRows; ++t) {
+                    v[t] = __builtin_nontemporal_load((const float*)a.X + idx);
+                    idx += a.ld;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < kRows; ++t) {
+                    v[t] = stager && ib + t < r1 ? __builtin_nontemporal_load((const float*)a.X + idx) : 0.0f;
+                    idx += a.ld;
+                }
             }
         }
     };
-    // One K step: multiply the A operands `cur` (32 rows from xsb) into acc,
-    // and meanwhile generate the A operands `nxt` of the 32 rows from nrow.
-    // The generator's vector instructions are interleaved with the matrix-core
-    // instructions, so both units work in the same wave.
+    // A chunk is two K steps of 32 rows.  Step h multiplies the A operands of
+    // its rows (au0 for h = 0, au1 for h = 1) with the staged X, and meanwhile
+    // generates the A operands of the next step (au1, then au0 for the next
+    // chunk), so the generator's vector instructions and the matrix-core
+    // instructions are issued by the same wave side by side.  The step is cut
+    // into four regions, one generated row pair and two column tiles each; the
+    // B operands of a region are read from LDS one region ahead.
     const bool active = lbase < k;                   // waves past k only stage X
     const int64_t lrow = a.row_offset + 8 * (L >> 4);
     auto gen_pair = [&](int64_t row, u32x4 (&au)[4], int p) {
@@ -172,30 +202,32 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) au[s][p] = pack_bf16(g0[s], g1[s]);
     };
-    auto step = [&](const __bf16* xsb, const u32x4 (&cur)[4], u32x4 (&nxt)[4], int64_t nrow) {
+    auto read_b = [&](const __bf16* xsb, int p, bf16x8 (&b)[2]) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            gen_pair(nrow + 2 * p, nxt, p);
+        for (int j = 0; j < 2; ++j)
+            b[j] = *(const bf16x8*)(xsb + ((2 * p + j) * 16 + (L & 15)) * kXsStride + 8 * (L >> 4));
+    };
+    auto chunk = [&](const __bf16* xsb, int64_t i0, u32x4 (&au0)[4], u32x4 (&au1)[4]) {
+        bf16x8 bq[2][2];
+        read_b(xsb, 0, bq[0]);
 #pragma unroll
-            for (int nt = 2 * p; nt < 2 * p + 2; ++nt) {
-                const bf16x8 b = *(const bf16x8*)(xsb + (nt * 16 + (L & 15)) * kXsStride + 8 * (L >> 4));
+        for (int r = 0; r < 8; ++r) {
+            const int h = r >> 2, p = r & 3;
+            if (r < 7) read_b(xsb + kMfmaRows * ((r + 1) >> 2), (r + 1) & 3, bq[(r + 1) & 1]);
+            gen_pair(lrow + i0 + kMfmaRows * (h + 1) + 2 * p, h == 0 ? au1 : au0, p);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc[s][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, cur[s]), b,
-                                                                         acc[s][nt], 0, 0, 0);
-            }
-        }
-        // 32 MFMAs, each followed by a share of the generator's instructions;
-        // the B operand of a column tile is read two tiles ahead
-        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                    acc[s][2 * p + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, h == 0 ? au0[s] : au1[s]), bq[r & 1][j], acc[s][2 * p + j], 0, 0, 0);
+            // the region's 8 MFMAs spread over its generator instructions
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
+            for (int j = 0; j < 8; ++j) {
                 __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                 __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
             }
-            if (nt < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
     u32x4 au0[4], au1[4];
@@ -206,25 +238,41 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     load_chunk(r0);
     int buf = 0;
     for (int64_t i0 = r0; i0 < r1; i0 += kMfmaChunk, buf ^= 1) {
-        if (want_cs) {
+        // every thread stages its column(s) (zeros past n), so the column
+        // tiles past n multiply zeros
+        __bf16* const dst = xs[buf] + col_ld * kXsStride + rgrp * kRows;
+        if constexpr (BF16_IN) {
+            if (want_cs) {
 #pragma unroll
-            for (int t = 0; t < 16; ++t) csum += (double)__builtin_fabsf(v[t]);
-        }
-        // every thread stages its column (zeros past n), so the column tiles
-        // past n multiply zeros
+                for (int t = 0; t < kRows; ++t) {
+                    csum += (double)__builtin_fabsf(__uint_as_float(d[t] << 16));
+                    csum1 += (double)__builtin_fabsf(__uint_as_float(d[t] & 0xffff0000u));
+                }
+            }
+            u32x4 c0, c1;                            // columns col_ld, col_ld + 1: rows 2u, 2u + 1 in word u
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            u32x4 pk;
+            for (int u = 0; u < 4; ++u) {
+                c0[u] = (d[2 * u] & 0xffffu) | (d[2 * u + 1] << 16);
+                c1[u] = (d[2 * u] >> 16) | (d[2 * u + 1] & 0xffff0000u);
+            }
+            *(u32x4*)dst = c0;
+            *(u32x4*)(dst + kXsStride) = c1;
+        } else {
+            if (want_cs) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) pk[t] = pack_bf16(v[8 * h + 2 * t], v[8 * h + 2 * t + 1]);
-            *(u32x4*)(xs[buf] + col_ld * kXsStride + rgrp * 16 + 8 * h) = pk;
+                for (int t = 0; t < kRows; ++t) csum += (double)__builtin_fabsf(v[t]);
+            }
+#pragma unroll
+            for (int h = 0; h < kRows / 8; ++h) {
+                u32x4 pk;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) pk[t] = pack_bf16(v[8 * h + 2 * t], v[8 * h + 2 * t + 1]);
+                *(u32x4*)(dst + 8 * h) = pk;
+            }
         }
         if (i0 + kMfmaChunk < r1) load_chunk(i0 + kMfmaChunk);
         __syncthreads();
-        if (active) {
-            step(xs[buf], au0, au1, lrow + i0 + kMfmaRows);
-            step(xs[buf] + kMfmaRows, au1, au0, lrow + i0 + kMfmaChunk);
-        }
+        if (active) chunk(xs[buf], i0, au0, au1);
     }
     // partial Y: tile (s, nt), element (row rho = 4 (L / 16) + e, column L % 16)
     float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
@@ -242,9 +290,14 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     if (a.part_cs != nullptr && blockIdx.y == 0) {
         __syncthreads();
         cs_sh[rgrp][col_ld] = csum;
+        if (BF16_IN) cs_sh[rgrp][col_ld + 1] = csum1;
         __syncthreads();
-        if (tid < n)
-            a.part_cs[(int64_t)blockIdx.x * ldp + cb + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+        if (tid < n) {
+            double t = 0.0;
+#pragma unroll
+            for (int g = 0; g < kGroups; ++g) t += cs_sh[g][tid];
+            a.part_cs[(int64_t)blockIdx.x * ldp + cb + tid] = t;
+        }
     }
 }
 

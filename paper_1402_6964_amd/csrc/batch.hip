@@ -60,7 +60,7 @@ constexpr int kGroupW128 = 4;     // nodes per FP64 merge (n <= 128): <= 512 row
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kLds = cmax(cmax(cmax(S16::lds_bytes(true, kWaves), S32::lds_bytes(true, kWaves)),
-                                  cmax(W64::lds_bytes(), W128::lds_bytes())),
+                                  cmax(W64::lds_bytes(true), W128::lds_bytes(true))),
                              cmax(cmax(M64::lds_bytes(), M128::lds_bytes()),
                                   cmax(sizeof(CoopTreeLds<16, kWaves>), sizeof(CoopTreeLds<32, kWaves>))));
 
@@ -330,8 +330,8 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
             }
         } else {
             const WideArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.n, 0, M.tree};
-            if (cls == CLS_W64) wide_slab<float, float, 8, kWaves, kRplW64, LOAD_ROW>(a, s0, smem);
-            else wide_slab<float, float, 16, kWaves, kRplW128, LOAD_ROW_BUF>(a, s0, smem);
+            if (cls == CLS_W64) wide_slab<float, float, 8, kWaves, kRplW64, LOAD_ROW_STAGED>(a, s0, smem);
+            else wide_slab<float, float, 16, kWaves, kRplW128, LOAD_ROW_STAGED>(a, s0, smem);
         }
         // slab group ticket: every wave releases its node stores first
         grid_release();

@@ -24,6 +24,7 @@ hipError_t launch_wide_f64_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32_rowbuf(const WideArgs& a, hipStream_t s);
+hipError_t launch_wide_f32_rowstg(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f64_rowbuf(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32w_rowbuf(const WideArgs& a, hipStream_t s);
 int rows_per_lane_f32(int n, bool staged);
@@ -63,7 +64,7 @@ hipError_t launch_leaf(Path p, int load, int n, const StreamArgs& a, hipStream_t
 }
 
 hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
-    const bool col = load == LOAD_COL, buf = load == LOAD_ROW_BUF;
+    const bool col = load == LOAD_COL, buf = load == LOAD_ROW_BUF, stg = load == LOAD_ROW_STAGED;
     if (a.n > 128) {
         switch (p) {
             case Path::F32: return col ? launch_xl_f32_col(a, s) : launch_xl_f32_row(a, s);
@@ -74,7 +75,10 @@ hipError_t launch_wide(Path p, int load, const WideArgs& a, hipStream_t s) {
     }
     switch (p) {
         case Path::F32:
-            return col ? launch_wide_f32_col(a, s) : buf ? launch_wide_f32_rowbuf(a, s) : launch_wide_f32_row(a, s);
+            return col   ? launch_wide_f32_col(a, s)
+                   : stg ? launch_wide_f32_rowstg(a, s)
+                   : buf ? launch_wide_f32_rowbuf(a, s)
+                         : launch_wide_f32_row(a, s);
         case Path::F64:
             return col ? launch_wide_f64_col(a, s) : buf ? launch_wide_f64_rowbuf(a, s) : launch_wide_f64_row(a, s);
         case Path::F32W:
@@ -118,6 +122,9 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     const int rpl_buf = f32 ? 12 : 5;
     if (p.wide && n <= 128 && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
+    // FP32 blocks of row-major input up to 128 columns: coalesced loads
+    // regrouped through LDS (12 rows per lane), whatever the row stride
+    if (p.wide && n <= 128 && f32 && !col) p.load = LOAD_ROW_STAGED;
     // above 128 columns: 8 waves x 32 columns, FP32 4 rows per lane, FP64 2
     // FP32 blocks of 33..64 columns: the blocked compact-WY leaf (8 waves,
     // 512-row blocks) when the configuration asks for it; the unblocked leaf
@@ -129,7 +136,7 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     }
     const int rpl = p.wy ? wy_block_rows() / 64
                     : n > 128 ? (f32 ? 4 : 2)
-                    : p.wide ? (p.load == LOAD_ROW_BUF ? rpl_buf
+                    : p.wide ? (p.load == LOAD_ROW_BUF || p.load == LOAD_ROW_STAGED ? rpl_buf
                                 : f32 ? (f32_8x8 ? 22 : (n <= 64 && !col ? 12 : 11)) : 4)
                              : (p.path == Path::F32 ? rows_per_lane_f32(n, p.load == LOAD_ROW_STAGED)
                                                     : rows_per_lane_f64(n, p.load == LOAD_ROW_STAGED));

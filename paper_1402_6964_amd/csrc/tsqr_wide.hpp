@@ -47,7 +47,12 @@ template <typename T, typename TI, int NW, int W, int RPL, bool RG = false> stru
     static constexpr int RW = NMAX * NW - W * NW * (NW - 1) / 2 + NMAX;   // FP64 slots per wave (bound)
     static constexpr size_t pv_elems() { return (size_t)2 * (RPL * 64 + 1); } // two pivot slots (T)
     static constexpr int NS = 8;                      // published reflector scalars per slot (FP64)
-    static constexpr size_t lds_bytes() { return ((size_t)(RG ? 0 : W * RW) + 2 * NS) * 8 + pv_elems() * sizeof(T); }
+    static constexpr size_t lds_core() { return ((size_t)(RG ? 0 : W * RW) + 2 * NS) * 8 + pv_elems() * sizeof(T); }
+    // staged row-major loads: two 64-row tiles of NMAX columns at an odd row
+    // stride (NMAX + 1 elements of 4 bytes), after the rest
+    static constexpr int SP = NMAX + 1;
+    static constexpr size_t stage_off() { return (lds_core() + 15) & ~(size_t)15; }
+    static constexpr size_t lds_bytes(bool staged = false) { return staged ? stage_off() + 2 * 64 * SP * 4 : lds_core(); }
     static constexpr size_t slot_bytes() { return (size_t)W * RW * 8; }   // global R of one workgroup (RG)
 
     // The W steps j = Q W + o (o = 0 .. W-1) whose pivot is local column Q of
@@ -216,6 +221,45 @@ __device__ __forceinline__ void wide_slab(const WideArgs& a, int64_t sid, unsign
                     else
                         v = __builtin_bit_cast(TI, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
                     x[r][c] = k < n ? (T)v : T(0);
+                }
+            }
+        } else if constexpr (LOAD == LOAD_ROW_STAGED) {
+            // Row-major rows read coalesced: thread t takes column t % NMAX of
+            // rows t / NMAX + (64 / NW) q, q < NW, of every 64-row chunk, so
+            // consecutive threads read consecutive addresses, and the loads of
+            // the whole block are issued at once (as many registers as the
+            // block itself).  Then chunk by chunk through an LDS tile (two
+            // buffers, one barrier per chunk) into the cyclic column layout:
+            // a lane reads row L of its wave's columns.  With the odd row
+            // stride both the tile writes and the column reads hit 64
+            // different banks.
+            static_assert(sizeof(TI) == 4 && sizeof(T) == 4, "staged wide loads are for FP32 input");
+            constexpr int NM = S::NMAX, SP = S::SP, RSTEP = 64 / NW;
+            const int tid = (int)threadIdx.x;
+            const int col = tid % NM, row0 = tid / NM;
+            const bool colok = col < n;
+            TI y[RPL][NW];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int64_t c0 = b0 + r * 64 + row0;
+                const TI* p = X + min(c0, a.m - 1) * a.ld + col;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    const int64_t i = c0 + RSTEP * q;
+                    y[r][q] = colok && i < r1 ? __builtin_nontemporal_load(p + (int64_t)(RSTEP * q) * a.ld) : TI(0);
+                }
+            }
+            TI* st = (TI*)(smem + S::stage_off());
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                TI* sb = st + (r & 1) * 64 * SP;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) sb[(row0 + RSTEP * q) * SP + col] = y[r][q];
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < NW; ++c) {
+                    const int k = wv + W * c;
+                    x[r][c] = k < n ? (T)sb[L * SP + k] : T(0);
                 }
             }
         } else {

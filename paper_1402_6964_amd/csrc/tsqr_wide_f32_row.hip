@@ -12,4 +12,9 @@ hipError_t launch_wide_f32_rowbuf(const WideArgs& a, hipStream_t stream) {
     if (a.n <= 64) return launch_wide_w<float, float, 4, LOAD_ROW_BUF, 16, 12>(a, stream);
     return launch_wide_w<float, float, 8, LOAD_ROW_BUF, 16, 12>(a, stream);
 }
+// Rows read coalesced and regrouped through LDS (16 columns per wave).
+hipError_t launch_wide_f32_rowstg(const WideArgs& a, hipStream_t stream) {
+    if (a.n <= 64) return launch_wide_w<float, float, 4, LOAD_ROW_STAGED, 16, 12>(a, stream);
+    return launch_wide_w<float, float, 8, LOAD_ROW_STAGED, 16, 12>(a, stream);
+}
 }  // namespace tsnmf

@@ -35,7 +35,7 @@ template <typename T, typename TI, int W, int LOAD, int NW = 16, int RPL = wide_
           int RPLD = 4>
 hipError_t launch_wide_w(const WideArgs& a, hipStream_t stream) {
     using S = Wide<T, TI, NW, W, RPL, RG>;
-    const size_t lds = S::lds_bytes();
+    const size_t lds = S::lds_bytes(LOAD == LOAD_ROW_STAGED);
     auto kern = tsqr_wide_kernel<T, TI, NW, W, RPL, LOAD, RG>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

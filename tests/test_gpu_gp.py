@@ -189,6 +189,26 @@ def test_mfma_bf16_matches_oracle(lib, m, n, k):
     assert np.linalg.norm(Yg - Yt) / np.linalg.norm(Yt) <= 1e-2
 
 
+@pytest.mark.parametrize("width,c0,n", [(131, 1, 128), (130, 2, 64), (130, 1, 64), (64, 0, 63)])
+def test_mfma_bf16_strided_views(lib, width, c0, n):
+    """BF16 column slices of a wider matrix: row length `width` (odd or even)
+    and a first column c0 that leaves the rows 2-byte aligned only (c0 odd) or
+    4-byte aligned (c0 even), so both the paired dword loads and the
+    element-wise loads run; the column sums of the same call are the FP64 sums
+    of the BF16 values."""
+    m, k = 9_001, 128
+    W = synth.random_matrix(m, width, dtype=torch.float32, seed_tag=36, dist="lognormal").to(torch.bfloat16)
+    Wd = W.cuda()
+    X = Wd[:, c0:c0 + n]
+    assert X.stride(0) == width and (X.data_ptr() % 4 == 0) == (c0 % 2 == 0)
+    Yg, csg = _gp(lib, X, k, 123, mode=lib.GP_MFMA_BF16, colsum=True)
+    Xh = W[:, c0:c0 + n].float().numpy()
+    s = Sums(Xh, 123, cols=all_groups(k))
+    assert (np.abs(Yg - s.Yk) / s.bound_bf16()).max() <= 1.0
+    d = np.abs(Xh.astype(np.float64)).sum(0)
+    assert np.max(np.abs(csg - d) / d) <= 1e-12
+
+
 def test_mfma_from_fp32_input(lib):
     """FP32 input on the matrix cores: X is rounded to BF16 (nearest even) while
     staged, so the reference is the oracle on bf16(X)."""

@@ -196,9 +196,8 @@ int tsnmf_tsqr_r_kron(const float* A, int64_t p, int32_t q, int64_t lda, double*
  * The arrays are read on the device when the work runs, so a captured graph
  * may be replayed with new pointers and shapes in the same arrays.  A matrix
  * whose entry is invalid (NULL X or R, n outside 1..TSNMF_MAX_BATCH_N, m < 1,
- * ld < n, or n > 64 with ld >= 2^23: those matrices are read in 64-row
- * chunks through 32-bit buffer offsets) is skipped; its R and column sums
- * are set to NaN when R is not NULL and n is in range.  Matrices are scheduled largest-first by m n^2.
+ * or ld < n) is skipped; its R and column sums are set to NaN when R is not
+ * NULL and n is in range.  Matrices are scheduled largest-first by m n^2.
  * Workspace: outside capture the call reads m, n and ld back (a host
  * synchronisation on `stream`) and grows its own device workspace as needed;
  * while capturing it uses what tsnmf_reserve_batched (or an earlier call)

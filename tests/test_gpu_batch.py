@@ -179,23 +179,23 @@ def test_invalid_entries_give_nan(lib):
         _check(res[q][0].cpu().numpy(), res[q][1].cpu().numpy(), good.cpu().numpy(), name=str(q))
 
 
-def test_row_stride_limit_of_the_128_column_class(lib):
-    """Matrices above 64 columns are read in 64-row chunks through 32-bit
-    buffer offsets, so ld >= 2^23 makes such an entry invalid (NaN outputs);
-    up to 64 columns the same stride is served by per-element loads."""
+def test_huge_row_stride_every_wide_class(lib):
+    """Row stride 2^23 (rows 32 MiB apart) for a 64- and a 128-column matrix
+    in the same store: both wide classes load each 64-row chunk with 64-bit
+    addresses and regroup it through LDS, so any stride is served."""
     ld = 1 << 23
     m = 100
     store = torch.zeros((m, ld), dtype=torch.float32, device="cuda")
-    A = synth.random_matrix(m, 64, dtype=torch.float32, seed_tag=202)
-    store[:, :64] = A.cuda()
+    A = synth.random_matrix(m, 128, dtype=torch.float32, seed_tag=202)
+    store[:, :128] = A.cuda()
     wide = synth.random_matrix(1_000, 128, dtype=torch.float32, seed_tag=203).cuda()
-    b = lib.Batch([store[:, :64], wide, wide])
-    b.ld.copy_(torch.tensor([ld, ld, 128], dtype=torch.int64))      # matrix 1: n = 128 with ld = 2^23
+    b = lib.Batch([store[:, :64], store[:, :128], wide])
+    assert b.ld.cpu().tolist() == [ld, ld, 128]
     b.run()
     torch.cuda.synchronize()
     res = b.results()
-    assert np.isnan(res[1][0].cpu().numpy()).all() and np.isnan(res[1][1].cpu().numpy()).all()
-    _check(res[0][0].cpu().numpy(), res[0][1].cpu().numpy(), A.numpy(), name="n = 64, ld = 2^23")
+    _check(res[0][0].cpu().numpy(), res[0][1].cpu().numpy(), A[:, :64].numpy(), name="n = 64, ld = 2^23")
+    _check(res[1][0].cpu().numpy(), res[1][1].cpu().numpy(), A.numpy(), name="n = 128, ld = 2^23")
     _check(res[2][0].cpu().numpy(), res[2][1].cpu().numpy(), wide.cpu().numpy(), name="n = 128, ld = 128")
     del store
 

@@ -41,7 +41,7 @@ constexpr int kWaves = 8;                                   // waves per workgro
 constexpr int64_t kMaxBatchN = 128;      // widest matrix of the batched call
 constexpr int kRplS16 = 8;        // one-wave classes: 512- and 320-row blocks
 constexpr int kRplS32 = 5;
-constexpr int kRplW64 = 24;       // 8 columns per wave
+constexpr int kRplW64 = 22;       // 8 columns per wave
 constexpr int kRplW128 = 12;      // 16 columns per wave
 constexpr int kRplM64 = 8;        // FP64 merges, 8 columns per wave
 constexpr int kRplM128 = 4;       // FP64 merges, 16 columns per wave
@@ -74,11 +74,11 @@ __host__ __device__ constexpr int class_of(int64_t n, int64_t ld) {
 __host__ __device__ constexpr int64_t class_block(int c) {
     return c == CLS_S16 ? S16::BR : c == CLS_S32 ? S32::BR : c == CLS_W64 ? W64::BR : W128::BR;
 }
-// Slabs are whole numbers of blocks (512, 320, 1536 and 768 rows).
+// Slabs are whole numbers of blocks (512, 320, 1408 and 768 rows).
 __host__ __device__ constexpr int64_t class_slab(int c) {
-    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4160 : c == CLS_W64 ? 7680 : 16128;
+    return c == CLS_S16 ? 4096 : c == CLS_S32 ? 4160 : c == CLS_W64 ? 7040 : 16128;
 }
-static_assert(4096 % S16::BR == 0 && 4160 % S32::BR == 0 && 7680 % W64::BR == 0 && 16128 % W128::BR == 0,
+static_assert(4096 % S16::BR == 0 && 4160 % S32::BR == 0 && 7040 % W64::BR == 0 && 16128 % W128::BR == 0,
               "default slabs are whole blocks");
 // Nodes per tree group.  For the one-wave classes a group must hold whole
 // items (multiples of kWaves slabs); 24 and 16 are near the fastest pass sizes.

@@ -114,10 +114,17 @@ constexpr int kMfmaRows = 32;                       // K of one 16x16x32 BF16 MF
 constexpr int kMfmaChunk = 64;                      // rows per barrier: two K steps
 constexpr int kXsStride = 72;                       // BF16 slots per staged column
 
-template <bool BF16_IN>
+// COOP (k <= 64, one 64-wide l-slice): the 8 waves share the slice.  Wave w
+// generates row t = w of every lane's 8-row K segment (one Philox block per
+// lane and K step instead of eight), the normals are exchanged through LDS
+// (ash[s][lane][t], double-buffered, one barrier per K step) so that every
+// wave holds the whole A operand, and wave w multiplies it with column tile
+// w of X.  Without it only the first wave of a small k would generate.
+template <bool BF16_IN, bool COOP>
 __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     __shared__ __align__(16) __bf16 xs[2][128 * kXsStride];   // [buffer][column][row]
     __shared__ double cs_sh[8][128];
+    __shared__ __align__(16) __bf16 ash[COOP ? 2 * 4 * 64 * 8 : 8];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
     // grid.z: block of 128 columns (columns cb .. cb + n - 1 of X and Y)
@@ -127,14 +134,15 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     const int NT = (n + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
-    const int lbase = blockIdx.y * 512 + wv * 64;    // first column l of this wave
+    const int lbase = blockIdx.y * 512 + (COOP ? 0 : wv * 64);   // first column l of this wave
     const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
     const bool want_cs = a.part_cs != nullptr && blockIdx.y == 0;
-    floatx4 acc[4][8];
+    constexpr int kTiles = COOP ? 1 : 8;              // column tiles of X per wave
+    floatx4 acc[4][kTiles];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < kTiles; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     // Staging.  FP32 input: thread (column tid % 128, row group tid / 128)
     // loads 16 rows of one column.  BF16 input: thread (column pair tid % 64,
     // row group tid / 64) loads 8 rows of two adjacent columns, one dword a
@@ -219,8 +227,9 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc[s][2 * p + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        __builtin_bit_cast(bf16x8, h == 0 ? au0[s] : au1[s]), bq[r & 1][j], acc[s][2 * p + j], 0, 0, 0);
+                    acc[s][(2 * p + j) % kTiles] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, h == 0 ? au0[s] : au1[s]), bq[r & 1][j], acc[s][(2 * p + j) % kTiles],
+                        0, 0, 0);
             // the region's 8 MFMAs spread over its generator instructions
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -230,8 +239,31 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
             __builtin_amdgcn_sched_barrier(0);
         }
     };
+    int ab = 0;                                      // exchange buffer of the next K step (COOP)
+    auto chunk_coop = [&](const __bf16* xsb, int64_t i0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float g[4];
+            gauss4(lrow + i0 + kMfmaRows * h + wv, q, a.key0, a.key1, g);
+            __bf16* aw = ash + ab * (4 * 64 * 8);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) aw[(s * 64 + L) * 8 + wv] = (__bf16)g[s];
+            __syncthreads();
+            u32x4 au[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) au[s] = *(const u32x4*)(aw + (s * 64 + L) * 8);
+            if (wv < NT) {
+                const bf16x8 b = *(const bf16x8*)(xsb + (wv * 16 + (L & 15)) * kXsStride + kMfmaRows * h + 8 * (L >> 4));
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au[s]), b, acc[s][0],
+                                                                        0, 0, 0);
+            }
+            ab ^= 1;
+        }
+    };
     u32x4 au0[4], au1[4];
-    if (active) {
+    if (!COOP && active) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) gen_pair(lrow + r0 + 2 * p, au0, p);
     }
@@ -272,19 +304,21 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
         }
         if (i0 + kMfmaChunk < r1) load_chunk(i0 + kMfmaChunk);
         __syncthreads();
-        if (active) chunk(xs[buf], i0, au0, au1);
+        if constexpr (COOP) chunk_coop(xs[buf], i0);
+        else if (active) chunk(xs[buf], i0, au0, au1);
     }
     // partial Y: tile (s, nt), element (row rho = 4 (L / 16) + e, column L % 16)
     float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
+        for (int t = 0; t < kTiles; ++t) {
+            const int nt = COOP ? wv : t;
             const int c = nt * 16 + (L & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int l = 4 * ((lbase >> 2) + 4 * (L >> 4) + e) + s;
-                if (nt < NT && c < n && l < k) P[(int64_t)l * ldp + c] = acc[s][nt][e];
+                if (nt < NT && c < n && l < k) P[(int64_t)l * ldp + c] = acc[s][t][e];
             }
         }
     if (a.part_cs != nullptr && blockIdx.y == 0) {
@@ -556,8 +590,15 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
         if (int st = profile_event(stream, &e0)) return st;
     }
     if (mfma) {
-        if (bf16) hipLaunchKernelGGL(gp_mfma_kernel<true>, grid, dim3(512), 0, stream, a);
-        else hipLaunchKernelGGL(gp_mfma_kernel<false>, grid, dim3(512), 0, stream, a);
+        // up to 64 columns of Y: one l-slice, shared by the 8 waves
+        const bool coop = k <= 64;
+        if (bf16) {
+            if (coop) hipLaunchKernelGGL((gp_mfma_kernel<true, true>), grid, dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((gp_mfma_kernel<true, false>), grid, dim3(512), 0, stream, a);
+        } else {
+            if (coop) hipLaunchKernelGGL((gp_mfma_kernel<false, true>), grid, dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((gp_mfma_kernel<false, false>), grid, dim3(512), 0, stream, a);
+        }
     } else {
         hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
     }

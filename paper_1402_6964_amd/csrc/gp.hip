@@ -114,17 +114,20 @@ constexpr int kMfmaRows = 32;                       // K of one 16x16x32 BF16 MF
 constexpr int kMfmaChunk = 64;                      // rows per barrier: two K steps
 constexpr int kXsStride = 72;                       // BF16 slots per staged column
 
-// COOP (k <= 64, one 64-wide l-slice): the 8 waves share the slice.  Wave w
-// generates row t = w of every lane's 8-row K segment (one Philox block per
-// lane and K step instead of eight), the normals are exchanged through LDS
-// (ash[s][lane][t], double-buffered, one barrier per K step) so that every
-// wave holds the whole A operand, and wave w multiplies it with column tile
-// w of X.  Without it only the first wave of a small k would generate.
-template <bool BF16_IN, bool COOP>
+// COOP = S in {1, 2} (k <= 64 S: S slices of 64 columns l): 8 / S waves
+// share each slice.  Wave w works on slice w % S, and its slot u = w / S
+// generates rows t = u S .. u S + S - 1 of every lane's 8-row K segment (S
+// Philox blocks per lane and K step instead of eight); the normals are
+// exchanged through LDS (ash[slice][s][lane][t], double-buffered, one barrier
+// per K step) so that every wave holds its slice's whole A operand, and slot u
+// multiplies it with column tiles u, u + 8 / S, ... of X.  Without it only the
+// first S waves of a small k would generate.  COOP = 0: one slice per wave.
+template <bool BF16_IN, int COOP>
 __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     __shared__ __align__(16) __bf16 xs[2][128 * kXsStride];   // [buffer][column][row]
     __shared__ double cs_sh[8][128];
-    __shared__ __align__(16) __bf16 ash[COOP ? 2 * 4 * 64 * 8 : 8];
+    constexpr int kAsh = COOP * 4 * 64 * 8;           // one buffer: S slices x 4 tiles x 64 lanes x 8 rows
+    __shared__ __align__(16) __bf16 ash[COOP ? 2 * kAsh : 8];
     const int tid = threadIdx.x;
     const int wv = tid >> 6, L = tid & 63;
     // grid.z: block of 128 columns (columns cb .. cb + n - 1 of X and Y)
@@ -134,10 +137,12 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     const int NT = (n + 15) / 16;
     const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
     const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
-    const int lbase = blockIdx.y * 512 + (COOP ? 0 : wv * 64);   // first column l of this wave
+    constexpr int kWps = COOP ? 8 / COOP : 1;         // waves per slice
+    const int slice = COOP ? wv % COOP : wv, slot = COOP ? wv / COOP : 0;
+    const int lbase = blockIdx.y * 512 + slice * 64;  // first column l of this wave
     const uint32_t q = (uint32_t)((lbase >> 2) + (L & 15));
     const bool want_cs = a.part_cs != nullptr && blockIdx.y == 0;
-    constexpr int kTiles = COOP ? 1 : 8;              // column tiles of X per wave
+    constexpr int kTiles = COOP ? COOP : 8;           // column tiles of X per wave
     floatx4 acc[4][kTiles];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -241,23 +246,32 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     };
     int ab = 0;                                      // exchange buffer of the next K step (COOP)
     auto chunk_coop = [&](const __bf16* xsb, int64_t i0) {
+        constexpr int S = COOP ? COOP : 1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            float g[4];
-            gauss4(lrow + i0 + kMfmaRows * h + wv, q, a.key0, a.key1, g);
-            __bf16* aw = ash + ab * (4 * 64 * 8);
+            __bf16* aw = ash + ab * kAsh + slice * (4 * 64 * 8);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) aw[(s * 64 + L) * 8 + wv] = (__bf16)g[s];
+            for (int j = 0; j < S; ++j) {
+                float g[4];
+                gauss4(lrow + i0 + kMfmaRows * h + slot * S + j, q, a.key0, a.key1, g);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) aw[(s * 64 + L) * 8 + slot * S + j] = (__bf16)g[s];
+            }
             __syncthreads();
             u32x4 au[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) au[s] = *(const u32x4*)(aw + (s * 64 + L) * 8);
-            if (wv < NT) {
-                const bf16x8 b = *(const bf16x8*)(xsb + (wv * 16 + (L & 15)) * kXsStride + kMfmaRows * h + 8 * (L >> 4));
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[s][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au[s]), b, acc[s][0],
-                                                                        0, 0, 0);
+            for (int j = 0; j < S; ++j) {
+                const int nt = slot + kWps * j;
+                if (nt < NT) {
+                    const bf16x8 b =
+                        *(const bf16x8*)(xsb + (nt * 16 + (L & 15)) * kXsStride + kMfmaRows * h + 8 * (L >> 4));
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au[s]), b,
+                                                                            acc[s][j], 0, 0, 0);
+                }
             }
             ab ^= 1;
         }
@@ -313,7 +327,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int t = 0; t < kTiles; ++t) {
-            const int nt = COOP ? wv : t;
+            const int nt = COOP ? slot + kWps * t : t;
             const int c = nt * 16 + (L & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -590,14 +604,18 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
         if (int st = profile_event(stream, &e0)) return st;
     }
     if (mfma) {
-        // up to 64 columns of Y: one l-slice, shared by the 8 waves
-        const bool coop = k <= 64;
+        // up to 128 columns of Y: 1 or 2 slices of 64, shared by the 8 waves
+        // (4 shared slices measured slower than 4 waves with a slice each:
+        // 3.9 against 3.6 ms at 2e7 x 128, k = 256)
+        const int coop = k <= 64 ? 1 : k <= 128 ? 2 : 0;
         if (bf16) {
-            if (coop) hipLaunchKernelGGL((gp_mfma_kernel<true, true>), grid, dim3(512), 0, stream, a);
-            else hipLaunchKernelGGL((gp_mfma_kernel<true, false>), grid, dim3(512), 0, stream, a);
+            if (coop == 1) hipLaunchKernelGGL((gp_mfma_kernel<true, 1>), grid, dim3(512), 0, stream, a);
+            else if (coop == 2) hipLaunchKernelGGL((gp_mfma_kernel<true, 2>), grid, dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((gp_mfma_kernel<true, 0>), grid, dim3(512), 0, stream, a);
         } else {
-            if (coop) hipLaunchKernelGGL((gp_mfma_kernel<false, true>), grid, dim3(512), 0, stream, a);
-            else hipLaunchKernelGGL((gp_mfma_kernel<false, false>), grid, dim3(512), 0, stream, a);
+            if (coop == 1) hipLaunchKernelGGL((gp_mfma_kernel<false, 1>), grid, dim3(512), 0, stream, a);
+            else if (coop == 2) hipLaunchKernelGGL((gp_mfma_kernel<false, 2>), grid, dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((gp_mfma_kernel<false, 0>), grid, dim3(512), 0, stream, a);
         }
     } else {
         hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);

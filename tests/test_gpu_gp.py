@@ -143,13 +143,13 @@ def test_gaussian_entries_simd(lib, offset):
     assert err.max() <= EPS_G
 
 
-@pytest.mark.parametrize("k", [512, 64])
+@pytest.mark.parametrize("k", [512, 256, 128, 64])
 @pytest.mark.parametrize("offset", [0, 2 ** 32 - 64])
 def test_gaussian_entries_bf16(lib, offset, k):
     """On the matrix cores the identity block gives bf16(G_gpu) exactly: equal
     to the BF16 rounding of the oracle's G except at entries within EPS_G rho
-    of a rounding boundary, which may differ by one BF16 step.  k = 64 runs
-    the mode in which the waves share one slice of G through LDS."""
+    of a rounding boundary, which may differ by one BF16 step.  k = 64 and
+    128 run the mode in which 8 or 4 waves share a slice of G through LDS."""
     X = torch.eye(128, dtype=torch.bfloat16, device="cuda")
     Y, _ = _gp(lib, X, k, 99, mode=lib.GP_MFMA_BF16, row_offset=offset)
     G = oph.gaussian_matrix(99, offset, 128, k)
@@ -178,7 +178,8 @@ def test_simd_fp32_matches_oracle(lib, m, n, k):
 
 
 @pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (33_333, 128, 512), (1000, 3, 1028), (20_000, 256, 128),
-                                   (5_000, 130, 64), (7_001, 40, 4), (12_345, 128, 36)])
+                                   (5_000, 130, 64), (7_001, 40, 4), (12_345, 128, 36), (6_000, 33, 100),
+                                   (9_001, 70, 200)])
 def test_mfma_bf16_matches_oracle(lib, m, n, k):
     X32 = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=32, dist="uniform")
     Xb = X32.to(torch.bfloat16)

@@ -433,6 +433,117 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
     }
 }
 
+// Small k (k <= 4 LG, LG = 8, 16 or 32): lane L of wave w owns the column
+// group q = L % LG (4 columns l) and columns 16 w .. 16 w + 15 of X, and
+// sub-stream s = L / LG of the 64 / LG the wave runs: rows s + (64 / LG) r,
+// r = 0..3, of each step of 4 (64 / LG) rows.  Every lane's 4 x 16 tile then
+// holds useful sums (the kernel above gives each lane 8 columns l of a
+// 512-wide range, most of them past a small k).  The step's G (one Philox
+// block per row and group, the first 4 LG x 64 / LG threads) and X rows are
+// staged in LDS with padded rows (the sub-streams of a read land in different
+// banks); waves whose columns of X all lie past n skip the products.  At the
+// end the sub-streams are added across lanes (permlane and DPP stages on the
+// lane bits of s, in a fixed order) and the lanes of sub-stream 0 write the
+// workgroup's partial.
+template <int LG>
+__global__ void __launch_bounds__(512) gp_simd_small_kernel(GpArgs a) {
+    constexpr int SSW = 64 / LG;                     // sub-streams per wave
+    constexpr int RS = kSimdRows * SSW;              // rows per step
+    constexpr int GST = 4 * LG + 4;                  // G row stride (floats)
+    constexpr int XST = 132;                         // X row stride (floats)
+    __shared__ __align__(16) float gs[2][RS * GST];
+    __shared__ __align__(16) float xsm[2][RS * XST];
+    __shared__ double cs_sh[4][128];
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, L = tid & 63;
+    const int cb = (int)blockIdx.z * 128;            // block of 128 columns
+    const int n = min(128, a.n - cb), k = a.k;
+    const int64_t ldp = a.n;
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int64_t r1 = min(a.m, r0 + a.rows_per_wg);
+    const int qq = L % LG, sub = L / LG;
+    const bool busy = 16 * wv < n;                   // this wave's columns of X exist
+    float acc[4][16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[e][c] = 0.0f;
+    double csum = 0.0;
+    const int gen_row = tid / LG, gen_q = tid % LG;  // generation: threads tid < RS LG
+    const int xc = tid & 127, xr = tid >> 7;         // staging: column, first row
+    int buf = 0;
+    for (int64_t i0 = r0; i0 < r1; i0 += RS, buf ^= 1) {
+        if (tid < RS * LG) {
+            float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};    // columns past k are not generated
+            if (4 * gen_q < k) gauss4(a.row_offset + i0 + gen_row, (uint32_t)gen_q, a.key0, a.key1, g);
+            *(float4*)&gs[buf][gen_row * GST + 4 * gen_q] = make_float4(g[0], g[1], g[2], g[3]);
+        }
+#pragma unroll
+        for (int j = 0; j < RS / 4; ++j) {
+            const int rr = xr + 4 * j;
+            const int64_t i = i0 + rr;
+            float v = 0.0f;
+            if (xc < n && i < r1) v = load_f32(a.X, i * a.ld + cb + xc, false);
+            csum += (double)__builtin_fabsf(v);
+            xsm[buf][rr * XST + xc] = v;
+        }
+        __syncthreads();
+        if (busy) {
+#pragma unroll
+            for (int r = 0; r < kSimdRows; ++r) {
+                const int row = sub + SSW * r;
+                const float4 g4 = *(const float4*)&gs[buf][row * GST + 4 * qq];
+                const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+                float xv[16];
+#pragma unroll
+                for (int c4 = 0; c4 < 4; ++c4) {
+                    const float4 t4 = *(const float4*)&xsm[buf][row * XST + 16 * wv + 4 * c4];
+                    xv[4 * c4] = t4.x;
+                    xv[4 * c4 + 1] = t4.y;
+                    xv[4 * c4 + 2] = t4.z;
+                    xv[4 * c4 + 3] = t4.w;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) acc[e][c] = __builtin_fmaf(gv[e], xv[c], acc[e][c]);
+            }
+        }
+    }
+    if (busy) {
+        // add the sub-streams: lane bits log2(LG) .. 5, highest first
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                float v = acc[e][c];
+                v = allreduce_stage<5>(v);
+                if constexpr (LG <= 16) v = allreduce_stage<4>(v);
+                if constexpr (LG <= 8) v = v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+                acc[e][c] = v;
+            }
+        if (sub == 0) {
+            float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int l = 4 * qq + e;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const int cc = 16 * wv + c;
+                    if (cc < n && l < k) P[(int64_t)l * ldp + cc] = acc[e][c];
+                }
+            }
+        }
+    }
+    if (a.part_cs != nullptr && blockIdx.y == 0) {
+        __syncthreads();
+        cs_sh[xr][xc] = csum;
+        __syncthreads();
+        if (tid < n)
+            a.part_cs[(int64_t)blockIdx.x * ldp + cb + tid] = cs_sh[0][tid] + cs_sh[1][tid] + cs_sh[2][tid] + cs_sh[3][tid];
+    }
+}
+
 // ---- the generator alone: G^T 1 ------------------------------------------------------
 //
 // The projection of a column of ones, with nothing read from memory: the same
@@ -618,7 +729,11 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
             else hipLaunchKernelGGL((gp_mfma_kernel<false, 0>), grid, dim3(512), 0, stream, a);
         }
     } else {
-        hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
+        // up to 128 columns of Y: lanes own one column group and split the rows
+        if (k <= 32) hipLaunchKernelGGL(gp_simd_small_kernel<8>, grid, dim3(512), 0, stream, a);
+        else if (k <= 64) hipLaunchKernelGGL(gp_simd_small_kernel<16>, grid, dim3(512), 0, stream, a);
+        else if (k <= 128) hipLaunchKernelGGL(gp_simd_small_kernel<32>, grid, dim3(512), 0, stream, a);
+        else hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
     }
     TSNMF_LAUNCH_CHECK();
     const bool prof_all = prof && profiling_all();

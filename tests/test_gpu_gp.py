@@ -130,14 +130,16 @@ def all_groups(k):
 
 # ---- G itself -------------------------------------------------------------------
 
+@pytest.mark.parametrize("k", [512, 128, 32])
 @pytest.mark.parametrize("offset", [0, 123_457, 2 ** 32 - 64, 3 * 2 ** 40 + 11])
-def test_gaussian_entries_simd(lib, offset):
+def test_gaussian_entries_simd(lib, offset, k):
     """Y of a 128 x 128 identity block at row offset o is G(o + j, l) exactly
     (one nonzero product per sum): every entry of G within EPS_G rho of the
-    oracle's, including rows whose index crosses 2^32 (the high counter word)."""
+    oracle's, including rows whose index crosses 2^32 (the high counter word).
+    k = 128 and 32 run the layout in which lanes split the rows."""
     X = torch.eye(128, dtype=torch.float32, device="cuda")
-    Y, _ = _gp(lib, X, 512, 0x1234_5678_9ABC_DEF0, mode=lib.GP_SIMD_F32, row_offset=offset)
-    G = oph.gaussian_matrix(0x1234_5678_9ABC_DEF0, offset, 128, 512)       # rows o .. o + 127
+    Y, _ = _gp(lib, X, k, 0x1234_5678_9ABC_DEF0, mode=lib.GP_SIMD_F32, row_offset=offset)
+    G = oph.gaussian_matrix(0x1234_5678_9ABC_DEF0, offset, 128, k)       # rows o .. o + 127
     err = np.abs(Y.T - G) / radius(G)
     print(f"max |G_gpu - G| / rho = {err.max():.3e}")
     assert err.max() <= EPS_G
@@ -164,7 +166,8 @@ def test_gaussian_entries_bf16(lib, offset, k):
 # ---- Y, entry by entry -------------------------------------------------------------
 
 @pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (20_000, 1, 8), (33_333, 7, 512), (40_001, 128, 512),
-                                   (3, 5, 4), (100, 128, 1028), (30_001, 200, 64), (10_000, 256, 516)])
+                                   (3, 5, 4), (100, 128, 1028), (30_001, 200, 64), (10_000, 256, 516),
+                                   (7_777, 128, 32), (12_001, 40, 100)])
 def test_simd_fp32_matches_oracle(lib, m, n, k):
     X = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=31, dist="lognormal")
     Yg, csg = _gp(lib, X.cuda(), k, 14026964, mode=lib.GP_SIMD_F32, colsum=True)

@@ -359,6 +359,7 @@ __global__ void __launch_bounds__(512) gp_mfma_kernel(GpArgs a) {
 // values and the wave's 16 X values (one broadcast) per row.
 constexpr int kSimdRows = 4;
 
+template <bool UPPER, bool PART>
 __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
     __shared__ __align__(16) float gs[2][kSimdRows][512];
     __shared__ __align__(16) float xsm[2][kSimdRows][128];
@@ -395,24 +396,35 @@ __global__ void __launch_bounds__(512) gp_simd_kernel(GpArgs a) {
             }
         }
         __syncthreads();
+        // waves whose columns of X lie past n skip their products (PART: n
+        // not a multiple of 128), and so does the upper half of the columns l
+        // when k <= 256 (UPPER false)
+        if (!PART || 16 * wv < n) {
 #pragma unroll
-        for (int rr = 0; rr < kSimdRows; ++rr) {
-            const float4 ga = *(const float4*)&gs[buf][rr][4 * L];
-            const float4 gb = *(const float4*)&gs[buf][rr][256 + 4 * L];
-            const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
-            float xv[16];
+            for (int rr = 0; rr < kSimdRows; ++rr) {
+                const float4 ga = *(const float4*)&gs[buf][rr][4 * L];
+                float gv[8] = {ga.x, ga.y, ga.z, ga.w, 0.0f, 0.0f, 0.0f, 0.0f};
+                if constexpr (UPPER) {
+                    const float4 gb = *(const float4*)&gs[buf][rr][256 + 4 * L];
+                    gv[4] = gb.x;
+                    gv[5] = gb.y;
+                    gv[6] = gb.z;
+                    gv[7] = gb.w;
+                }
+                float xv[16];
 #pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-                const float4 t4 = *(const float4*)&xsm[buf][rr][16 * wv + 4 * c4];
-                xv[4 * c4] = t4.x;
-                xv[4 * c4 + 1] = t4.y;
-                xv[4 * c4 + 2] = t4.z;
-                xv[4 * c4 + 3] = t4.w;
+                for (int c4 = 0; c4 < 4; ++c4) {
+                    const float4 t4 = *(const float4*)&xsm[buf][rr][16 * wv + 4 * c4];
+                    xv[4 * c4] = t4.x;
+                    xv[4 * c4 + 1] = t4.y;
+                    xv[4 * c4 + 2] = t4.z;
+                    xv[4 * c4 + 3] = t4.w;
+                }
+#pragma unroll
+                for (int e = 0; e < (UPPER ? 8 : 4); ++e)
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) acc[e][c] = __builtin_fmaf(gv[e], xv[c], acc[e][c]);
             }
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-#pragma unroll
-                for (int c = 0; c < 16; ++c) acc[e][c] = __builtin_fmaf(gv[e], xv[c], acc[e][c]);
         }
     }
     float* P = a.part + (int64_t)blockIdx.x * k * ldp + cb;
@@ -733,7 +745,9 @@ int gauss_proj_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags,
         if (k <= 32) hipLaunchKernelGGL(gp_simd_small_kernel<8>, grid, dim3(512), 0, stream, a);
         else if (k <= 64) hipLaunchKernelGGL(gp_simd_small_kernel<16>, grid, dim3(512), 0, stream, a);
         else if (k <= 128) hipLaunchKernelGGL(gp_simd_small_kernel<32>, grid, dim3(512), 0, stream, a);
-        else hipLaunchKernelGGL(gp_simd_kernel, grid, dim3(512), 0, stream, a);
+        else if (k <= 256) hipLaunchKernelGGL((gp_simd_kernel<false, true>), grid, dim3(512), 0, stream, a);
+        else if (n % 128 != 0) hipLaunchKernelGGL((gp_simd_kernel<true, true>), grid, dim3(512), 0, stream, a);
+        else hipLaunchKernelGGL((gp_simd_kernel<true, false>), grid, dim3(512), 0, stream, a);
     }
     TSNMF_LAUNCH_CHECK();
     const bool prof_all = prof && profiling_all();

@@ -167,7 +167,7 @@ def test_gaussian_entries_bf16(lib, offset, k):
 
 @pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (20_000, 1, 8), (33_333, 7, 512), (40_001, 128, 512),
                                    (3, 5, 4), (100, 128, 1028), (30_001, 200, 64), (10_000, 256, 516),
-                                   (7_777, 128, 32), (12_001, 40, 100)])
+                                   (7_777, 128, 32), (12_001, 40, 100), (6_001, 30, 200), (4_000, 50, 300)])
 def test_simd_fp32_matches_oracle(lib, m, n, k):
     X = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=31, dist="lognormal")
     Yg, csg = _gp(lib, X.cuda(), k, 14026964, mode=lib.GP_SIMD_F32, colsum=True)

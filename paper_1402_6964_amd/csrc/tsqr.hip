@@ -113,10 +113,10 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     // (8 columns x 16 rows per lane), else 4 (16 columns per wave)
     const bool f32_8x8 = p.path == Path::F32 && n <= 64 && col;
     p.waves = !p.wide ? 1 : (n > 64 || f32_8x8 ? 8 : 4);
-    // wide row-major input goes through buffer resources when the row offsets
-    // of a 64-row chunk fit their 32 bits (FP32 blocks: 12 rows per lane;
-    // FP64 blocks: 5); otherwise per-element loads (FP32: 12 up to 64
-    // columns, else 11; FP64: 4)
+    // wide row-major input with FP64 blocks (FP64 input, or FP32 input with
+    // FP64 leaves) goes through buffer resources when the row offsets of a
+    // 64-row chunk fit their 32 bits (5 rows per lane), otherwise through
+    // per-element loads (4); FP32 blocks are staged below
     const int64_t esize = dt == TSNMF_F64 ? 8 : 4;
     const bool f32 = p.path == Path::F32;
     const int rpl_buf = f32 ? 12 : 5;

@@ -77,6 +77,23 @@ __device__ __forceinline__ double sqrt_normal(double x) {
     return __builtin_fma(d, h, g);
 }
 
+// sqrt(x) and 1 / sqrt(x) for x in the normal FP64 range, from the same
+// refinement as sqrt_normal: after the coupled Newton step h = 1 / (2
+// sqrt(x)) has about twice the estimate's correct bits (enough for the
+// reflector scalars that use it), and g gets the residual correction.
+struct SqrtRsq {
+    double g, y;
+};
+__device__ __forceinline__ SqrtRsq sqrt_rsq_normal(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    return {__builtin_fma(d, h, g), 2.0 * h};
+}
+
 // T: arithmetic of the block (its dot products and updates); TI: input
 // element type; R, alpha, sigma and the reflector scalars are kept in FP64
 // (TR), so that the running factor of a long slab does not accumulate FP32
@@ -161,25 +178,30 @@ template <typename T, typename TI, int N, int RPL> struct Small {
             // sigma > 0 and beta is nonzero.
             const bool live = sigma != TR(0);
             if (live) {
-                TR beta, inv_beta, s;
+                TR beta, inv_beta, tau, w;
                 if constexpr (sizeof(T) == 4) {
                     // FP32 block: sigma is a nonzero FP32 value, so alpha^2 +
-                    // sigma and beta (alpha - beta) lie far inside the normal
-                    // FP64 range, and one reciprocal serves both scalars.
-                    const TR nrm = sqrt_normal(fma_t(alpha, alpha, sigma));
-                    beta = alpha >= TR(0) ? -nrm : nrm;
-                    const TR amb = alpha - beta;
-                    const TR q = rcp_fast<TR>(beta * amb);
-                    inv_beta = amb * q;
-                    s = beta * q;                                            // 1 / (alpha - beta)
+                    // sigma and |alpha| + nrm lie far inside the normal FP64
+                    // range.  With beta = -sign(alpha) nrm: 1 / beta =
+                    // -sign(alpha) / nrm, tau = 1 + |alpha| / nrm, and
+                    // 1 / (alpha - beta) = sign(alpha) / (|alpha| + nrm), whose
+                    // sign goes into D, so one reciprocal (no cancellation)
+                    // follows the square root on the step's critical path.
+                    const SqrtRsq sr = sqrt_rsq_normal(fma_t(alpha, alpha, sigma));
+                    const TR aa = abs_t(alpha);
+                    beta = __builtin_copysign(sr.g, -alpha);
+                    inv_beta = __builtin_copysign(sr.y, -alpha);
+                    tau = fma_t(aa, sr.y, TR(1));
+                    const TR t = rcp_fast<TR>(aa + sr.g);
+                    w = fma_t(t, __builtin_copysign(TR(1), alpha) * DR, rj);
                 } else {
                     const TR nrm = sqrt_t<TR>(fma_t(alpha, alpha, sigma));
                     beta = alpha >= TR(0) ? -nrm : nrm;
                     inv_beta = rcp_fast<TR>(beta);
-                    s = rcp_fast<TR>(alpha - beta);
+                    const TR s = rcp_fast<TR>(alpha - beta);
+                    tau = (beta - alpha) * inv_beta;
+                    w = fma_t(s, DR, rj);
                 }
-                const TR tau = (beta - alpha) * inv_beta;
-                const TR w = fma_t(s, DR, rj);
                 TR rn = fma_t(-tau, w, rj);
                 if (vi == 0) rn = beta;
                 row[vi] = rn;

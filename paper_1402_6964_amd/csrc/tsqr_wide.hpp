@@ -96,27 +96,32 @@ template <typename T, typename TI, int NW, int W, int RPL, bool RG = false> stru
                     // R(j, j): first entry of the owner's row j (lane 0 holds local column Q)
                     const double alpha = RG ? lane_bcast(rj_pre, 0) : Rw[off];
                     const bool lv = sigma != 0.0;
-                    double beta, inv_beta, s_;
+                    double beta, inv_beta, s_, tau_;
                     if constexpr (sizeof(T) == 4) {
                         // FP32 block: a live sigma is a nonzero FP32 value, so
-                        // alpha^2 + sigma and beta (alpha - beta) are normal
-                        // FP64 numbers; one reciprocal gives both scalars.
-                        const double nrm = sqrt_normal(__builtin_fma(alpha, alpha, sigma));
-                        beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
-                        const double amb = alpha - beta;
-                        const double q = rcp_fast<double>(beta * amb);         // unused unless live
-                        inv_beta = amb * q;
-                        s_ = beta * q;
+                        // alpha^2 + sigma and |alpha| + nrm are normal FP64
+                        // numbers.  With beta = -sign(alpha) nrm: 1 / beta and
+                        // tau = 1 + |alpha| / nrm come from the refined
+                        // reciprocal square root, and 1 / (alpha - beta) =
+                        // sign(alpha) / (|alpha| + nrm) takes one reciprocal
+                        // (the results are unused unless live).
+                        const SqrtRsq sr = sqrt_rsq_normal(__builtin_fma(alpha, alpha, sigma));
+                        const double aa = __builtin_fabs(alpha);
+                        beta = lv ? __builtin_copysign(sr.g, -alpha) : alpha;
+                        inv_beta = __builtin_copysign(sr.y, -alpha);
+                        s_ = __builtin_copysign(rcp_fast<double>(aa + sr.g), alpha);
+                        tau_ = __builtin_fma(aa, sr.y, 1.0);
                     } else {
                         const double nrm = __builtin_sqrt(__builtin_fma(alpha, alpha, sigma));
                         beta = lv ? (alpha >= 0.0 ? -nrm : nrm) : alpha;
                         inv_beta = rcp_fast<double>(beta);
                         s_ = rcp_fast<double>(alpha - beta);
+                        tau_ = (beta - alpha) * inv_beta;
                     }
                     if (L == 0) {
                         sc[0] = beta;
                         sc[1] = lv ? s_ : 0.0;                               // s = 1 / (alpha - beta)
-                        sc[2] = lv ? (beta - alpha) * inv_beta : 0.0;        // tau
+                        sc[2] = lv ? tau_ : 0.0;                             // tau
                         sc[3] = lv ? inv_beta : 0.0;                         // 1 / beta for the block update
                     }
                 }

@@ -4,7 +4,7 @@
 #include "tsqr_wide_inst.hpp"
 
 namespace tsnmf {
-hipError_t launch_xl_f32_row(const WideArgs& a, hipStream_t s) { return launch_wide_xl<float, float, LOAD_ROW>(a, s); }
+hipError_t launch_xl_f32_row(const WideArgs& a, hipStream_t s) { return launch_wide_xl<float, float, LOAD_ROW_STAGED>(a, s); }
 hipError_t launch_xl_f32_col(const WideArgs& a, hipStream_t s) { return launch_wide_xl<float, float, LOAD_COL>(a, s); }
 hipError_t launch_xl_f64_row(const WideArgs& a, hipStream_t s) { return launch_wide_xl<double, double, LOAD_ROW>(a, s); }
 hipError_t launch_xl_f64_col(const WideArgs& a, hipStream_t s) { return launch_wide_xl<double, double, LOAD_COL>(a, s); }

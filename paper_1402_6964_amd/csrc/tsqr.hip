@@ -123,7 +123,8 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     if (p.wide && n <= 128 && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
     // FP32 blocks of row-major input up to 128 columns: coalesced loads
-    // regrouped through LDS (12 rows per lane), whatever the row stride
+    // regrouped through LDS (12 rows per lane), whatever the row stride (the
+    // kernels above 128 columns stage FP32 row-major input the same way)
     if (p.wide && n <= 128 && f32 && !col) p.load = LOAD_ROW_STAGED;
     // above 128 columns: 8 waves x 32 columns, FP32 4 rows per lane, FP64 2
     // FP32 blocks of 33..64 columns: the blocked compact-WY leaf (8 waves,

@@ -182,7 +182,7 @@ def test_simd_fp32_matches_oracle(lib, m, n, k):
 
 @pytest.mark.parametrize("m,n,k", [(50_003, 25, 64), (33_333, 128, 512), (1000, 3, 1028), (20_000, 256, 128),
                                    (5_000, 130, 64), (7_001, 40, 4), (12_345, 128, 36), (6_000, 33, 100),
-                                   (9_001, 70, 200)])
+                                   (9_001, 70, 200), (3, 5, 4), (65, 7, 100)])
 def test_mfma_bf16_matches_oracle(lib, m, n, k):
     X32 = synth.random_matrix(m, n, dtype=torch.float32, seed_tag=32, dist="uniform")
     Xb = X32.to(torch.bfloat16)

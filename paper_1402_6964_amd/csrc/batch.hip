@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kWaves * 64) batch_kernel(BatchHdr* hdr, const
         const int ns = (int)min((int64_t)class_per_item(cls), M.leaves - s0);
         if (cls == CLS_S16 || cls == CLS_S32) {
             if (wv < ns) {
-                const StreamArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.tree};
+                const StreamArgs a{M.X, M.m, M.ld, M.slab, M.leaves, M.tree, 0};
                 if (cls == CLS_S16) small_slab<float, float, 16, kRplS16, LOAD_ROW_STAGED, kWaves>(a, s0 + wv, smem, wv);
                 else small_slab<float, float, 32, kRplS32, LOAD_ROW_STAGED, kWaves>(a, s0 + wv, smem, wv);
             }

@@ -122,10 +122,14 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     const int rpl_buf = f32 ? 12 : 5;
     if (p.wide && n <= 128 && p.load == LOAD_ROW && 64LL * ld * esize < ((int64_t)1 << 31))
         p.load = LOAD_ROW_BUF;
-    // FP32 blocks of row-major input up to 128 columns: coalesced loads
+    // FP32 blocks of row-major input of 48..128 columns: coalesced loads
     // regrouped through LDS (12 rows per lane), whatever the row stride (the
-    // kernels above 128 columns stage FP32 row-major input the same way)
-    if (p.wide && n <= 128 && f32 && !col) p.load = LOAD_ROW_STAGED;
+    // kernels above 128 columns stage FP32 row-major input the same way).
+    // Below 48 columns neither load wins throughout (2e7 rows: 33 columns
+    // 3.47 ms direct against 3.66 staged, 40 columns 4.34 against 4.07, 44
+    // columns 4.07 against 4.34, 48 columns 4.85 against 4.60), and the
+    // direct loads are kept.
+    if (p.wide && n >= 48 && n <= 128 && f32 && !col) p.load = LOAD_ROW_STAGED;
     // above 128 columns: 8 waves x 32 columns, FP32 4 rows per lane, FP64 2
     // FP32 blocks of 33..64 columns: the blocked compact-WY leaf (8 waves,
     // 512-row blocks) when the configuration asks for it; the unblocked leaf

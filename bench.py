@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK = 157.3    # FP32 vector/matrix peak of MI355X (256 CUs x 2.4 GHz, packed FP32)
-FP32_UNPACKED_PEAK = 78.6   # FP32 FMA on the vector ALUs without packed instructions (this build)
+FP32_UNPACKED_PEAK = 78.6   # FP32 FMA on the vector ALUs without packed instructions (all HIP code here is compiled without them)
 METRIC = "TSQR GB/s of X (fraction of HBM peak) + batched matrices/s at fixed R error"
 WORKLOAD = {"workload": "flow_cytometry", "m": 10_000_000, "n": 25, "dtype_in": "fp32",
             "layout": "row-major", "bytes": 10_000_000 * 25 * 4, "r": 16}
@@ -426,7 +426,7 @@ def extras(torch, tsnmf, synth, dev, check=True, tuned=None):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
     # the all-core oracle's worker processes start before this process
@@ -525,7 +525,7 @@ def main():
         # flop/B, below the 19.7 flop/B ridge of the 157.3 TF/s FP32 peak, so
         # its roof is HBM.  The ALU view rides along: against 157.3 TF/s, and
         # against 78.6 TF/s, the FP32 FMA rate of the vector ALUs without the
-        # packed instructions this build does not emit.
+        # packed instructions that the library's kernels are compiled without.
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": LEAF_KERNEL, "kernel_avg_ms": round(leaf_avg_ms, 5),

@@ -1,7 +1,7 @@
 """GPU parity of tsnmf_tsqr_r (Sec. 3.1 R factor, Sec. 3.3 column sums) against
 the CPU oracle, through the C ABI.
 
-Tolerances (spec bounds): ||R^T R - X^T X||_F / ||X||_F^2 <= 1e-6 for
+Tolerances (the accuracy targets of the path): ||R^T R - X^T X||_F / ||X||_F^2 <= 1e-6 for
 FP32 row blocks and <= 1e-12 for the FP64 path; column 2-norm relative error
 <= 1e-5 (FP32).  Element-wise R comparisons use inputs with full column rank
 and moderate condition number, where R is unique and first-order perturbation

@@ -6,6 +6,7 @@
 #include <float.h>
 
 #include "common.hpp"
+#include "wave.hpp"
 
 namespace tsnmf {
 
@@ -13,38 +14,104 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Block-wide argmax over (value, index) pairs; ties go to the smaller index.
-// Every thread gets the result.  `sv`/`si` are LDS scratch of kThreads entries.
-__device__ void block_argmax(double v, int idx, double* sv, int* si, double* out_v, int* out_i) {
-    const int t = threadIdx.x;
-    sv[t] = v;
-    si[t] = idx;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            const double ov = sv[t + s];
-            const int oi = si[t + s];
-            if (ov > sv[t] || (ov == sv[t] && oi < si[t])) {
-                sv[t] = ov;
-                si[t] = oi;
-            }
-        }
-        __syncthreads();
+// v as held by lane `src` (wave-uniform).
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One 64-lane wave: the sum of v over the lanes by the permlane and DPP
+// stages (partners L ^ 32, 16, 15, 7, 2, 1: every stage adds a disjoint set of
+// lanes, and partners add the same two values), taken from lane 0 so that it
+// is wave-uniform by construction.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = allreduce_stage<5>(v);
+    v = allreduce_stage<4>(v);
+    v = allreduce_stage<3>(v);
+    v = allreduce_stage<2>(v);
+    v = allreduce_stage<1>(v);
+    v = allreduce_stage<0>(v);
+    return lane_value(v, 0);
+}
+
+// The value of lane L ^ m at the stage on lane bit BIT (m as in wave_sum).
+template <int BIT> __device__ __forceinline__ uint32_t partner_u32(uint32_t x) {
+    if constexpr (BIT == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    } else if constexpr (BIT == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, DppCtrl<BIT>::v, 0xf, 0xf, false);
     }
-    *out_v = sv[0];
-    *out_i = si[0];
+}
+
+template <int BIT> __device__ __forceinline__ void argmax_stage(double& v, int& idx) {
+    const double ov = mk64(partner_u32<BIT>(hi32(v)), partner_u32<BIT>(lo32(v)));
+    const int oi = (int)partner_u32<BIT>((uint32_t)idx);
+    if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+    }
+}
+
+// The (value, index) pair with the larger value, ties to the smaller index,
+// over the wave; lane 0's result is the one returned to every lane.
+__device__ __forceinline__ void wave_argmax_pair(double& v, int& idx) {
+    argmax_stage<5>(v, idx);
+    argmax_stage<4>(v, idx);
+    argmax_stage<3>(v, idx);
+    argmax_stage<2>(v, idx);
+    argmax_stage<1>(v, idx);
+    argmax_stage<0>(v, idx);
+    v = lane_value(v, 0);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+}
+
+// Index of the largest v over the wave, ties to the smaller index; lanes
+// without a candidate pass (-inf, 64), so 64 means none.
+__device__ __forceinline__ int wave_argmax(double v, int idx) {
+    wave_argmax_pair(v, idx);
+    return idx;
+}
+
+// Block-wide argmax over (value, index) pairs; ties go to the smaller index.
+// Every thread gets the result: each wave reduces by shuffles, then every
+// thread combines the waves' pairs in wave order (the winner is the same in
+// any order: larger value, then smaller index).  `sv`/`si` are LDS scratch of
+// at least kThreads / 64 entries.
+__device__ void block_argmax(double v, int idx, double* sv, int* si, double* out_v, int* out_i) {
+    wave_argmax_pair(v, idx);
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = v;
+        si[threadIdx.x >> 6] = idx;
+    }
+    __syncthreads();
+    v = sv[0];
+    idx = si[0];
+    for (int w = 1; w < kThreads / 64; ++w) {
+        const double ov = sv[w];
+        const int oi = si[w];
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+    *out_v = v;
+    *out_i = idx;
     __syncthreads();
 }
 
+// Block-wide sum: per wave by shuffles, then the waves' sums in wave order.
 __device__ double block_sum(double v, double* sv) {
-    const int t = threadIdx.x;
-    sv[t] = v;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sv[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (t < s) sv[t] += sv[t + s];
-        __syncthreads();
-    }
-    const double r = sv[0];
+    double r = sv[0];
+    for (int w = 1; w < kThreads / 64; ++w) r += sv[w];
     __syncthreads();
     return r;
 }
@@ -55,13 +122,21 @@ __device__ double block_sum(double v, double* sv) {
 // with u = Z(:, j*) / ||Z(:, j*)||.  Thread j owns column j (n <= 256); the
 // rows may be as many as the projection's k (p <= kSpaMaxRows), so that SPA
 // also runs on (G^T X) D^{-1} (Sec. 2.3, Sec. 3.3).
+// With ZL, Z lives in LDS after u (p (n + 1) doubles), else in `Zg`.
 constexpr int kSpaMaxRows = 4096;
+constexpr size_t kLdsCap = 150 * 1024;   // dynamic LDS these kernels may take
+__host__ __device__ constexpr bool spa_z_in_lds(int p, int n) {
+    return (size_t)p * (n + 1) * sizeof(double) <= kLdsCap;
+}
+template <bool ZL>
 __global__ void __launch_bounds__(kThreads) spa_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                        const double* __restrict__ colscale, int r, int* K,
-                                                       double* score, int* info, double* Z) {
-    __shared__ double sv[kThreads];
-    __shared__ int si[kThreads];
-    __shared__ double u[kSpaMaxRows];
+                                                       double* score, int* info, double* Zg) {
+    extern __shared__ double spa_lds[];
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    double* u = spa_lds;
+    double* Z = ZL ? spa_lds + p : Zg;
     const int j = threadIdx.x;
     const bool col = j < n;
     const double sc = (col && colscale != nullptr) ? 1.0 / colscale[j] : 1.0;
@@ -72,6 +147,7 @@ __global__ void __launch_bounds__(kThreads) spa_kernel(const double* __restrict_
     for (int t = 0; t < r; ++t) {
         double s = 0.0;
         if (col)
+#pragma unroll 4
             for (int i = 0; i < p; ++i) {
                 const double z = Z[(int64_t)i * n + j];
                 s = __builtin_fma(z, z, s);
@@ -91,7 +167,9 @@ __global__ void __launch_bounds__(kThreads) spa_kernel(const double* __restrict_
         __syncthreads();
         if (col) {
             double w = 0.0;
+#pragma unroll 4
             for (int i = 0; i < p; ++i) w = __builtin_fma(u[i], Z[(int64_t)i * n + j], w);
+#pragma unroll 4
             for (int i = 0; i < p; ++i) Z[(int64_t)i * n + j] -= u[i] * w;
         }
         __syncthreads();
@@ -153,7 +231,7 @@ __global__ void __launch_bounds__(kThreads) gp_select_kernel(const float* __rest
 // min_{y >= 0} ||A y - M(:, i)|| has the same minimiser as
 // min_{y >= 0} ||R_A y - C(:, i)|| (Q_A is orthogonal), with the same
 // gradient A^T (b - A y) = R_A^T (c - R_A y).
-// Stage 2 (one thread per column): Lawson-Hanson on the r x r problem, the
+// Stage 2 (one wave per column): Lawson-Hanson on the r x r problem, the
 // unconstrained subproblems solved by Householder QR of R_A(:, P).
 
 struct NnlsWork {
@@ -161,7 +239,6 @@ struct NnlsWork {
     double* RA;       // r x r column-major
     double* C;        // r x n column-major
     double* anorm1;   // ||A||_1; the next slot is 1.0 when K holds an index outside [0, n)
-    double* scratch;  // per column: r * r + 6 r doubles
     const int* skip;  // when non-null and nonzero, do nothing (XRAY after an early stop)
 };
 
@@ -173,12 +250,21 @@ __device__ int bad_indices(const int* K, int r, int n) {
     return bad;
 }
 
+// With AL, [A | M] lives in LDS with an odd leading dimension (conflict-free
+// column walks by consecutive threads), else in the workspace with ld p.
+__host__ __device__ constexpr int nnls_qr_ld(int p, bool al) { return al ? (p | 1) : p; }
+__host__ __device__ constexpr bool nnls_aug_in_lds(int p, int n, int r) {
+    return (size_t)nnls_qr_ld(p, true) * (r + n) * sizeof(double) <= kLdsCap;
+}
+template <bool AL>
 __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                            const int* __restrict__ K, int r, NnlsWork w) {
+    extern __shared__ double qr_lds[];
     __shared__ double sv[kThreads];
     __shared__ double v[256];
     __shared__ int badk;
     const int t = threadIdx.x;
+    const int lda = nnls_qr_ld(p, AL);
     if (w.skip != nullptr && w.skip[0] != 0) return;
     if (t == 0) {
         badk = bad_indices(K, r, n);
@@ -187,16 +273,16 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     __syncthreads();
     if (badk) return;
     const int ncol = r + n;
-    double* aug = w.aug;
+    double* aug = AL ? qr_lds : w.aug;
     for (int c = t; c < ncol; c += kThreads) {
         const int src = c < r ? K[c] : c - r;
-        for (int i = 0; i < p; ++i) aug[(int64_t)c * p + i] = M[(int64_t)src * ldm + i];
+        for (int i = 0; i < p; ++i) aug[(int64_t)c * lda + i] = M[(int64_t)src * ldm + i];
     }
     // ||A||_1 = largest column l1 norm of A
     double a1 = 0.0;
     for (int c = t; c < r; c += kThreads) {
         double s = 0.0;
-        for (int i = 0; i < p; ++i) s += __builtin_fabs(aug[(int64_t)c * p + i]);
+        for (int i = 0; i < p; ++i) s += __builtin_fabs(aug[(int64_t)c * lda + i]);
         a1 = s > a1 ? s : a1;
     }
     sv[t] = a1;
@@ -208,7 +294,7 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     if (t == 0) *w.anorm1 = sv[0];
     __syncthreads();
     for (int j = 0; j < r && j < p; ++j) {
-        double* col = aug + (int64_t)j * p;
+        double* col = aug + (int64_t)j * lda;
         double part = 0.0;
         for (int i = j + 1 + t; i < p; i += kThreads) part = __builtin_fma(col[i], col[i], part);
         const double sigma = block_sum(part, sv);
@@ -223,10 +309,12 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
         for (int i = j + t; i < p; i += kThreads) v[i] = (i == j) ? 1.0 : col[i] * sc;
         __syncthreads();
         for (int c = j + 1 + t; c < ncol; c += kThreads) {
-            double* cc = aug + (int64_t)c * p;
+            double* cc = aug + (int64_t)c * lda;
             double d = 0.0;
+#pragma unroll 4
             for (int i = j; i < p; ++i) d = __builtin_fma(v[i], cc[i], d);
             d *= tau;
+#pragma unroll 4
             for (int i = j; i < p; ++i) cc[i] -= d * v[i];
         }
         __syncthreads();
@@ -236,145 +324,175 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     }
     // R_A (rows beyond p stay zero) and C
     for (int c = t; c < r; c += kThreads)
-        for (int i = 0; i < r; ++i) w.RA[(int64_t)c * r + i] = (i <= c && i < p) ? aug[(int64_t)c * p + i] : 0.0;
+        for (int i = 0; i < r; ++i) w.RA[(int64_t)c * r + i] = (i <= c && i < p) ? aug[(int64_t)c * lda + i] : 0.0;
     for (int c = t; c < n; c += kThreads)
-        for (int i = 0; i < r; ++i) w.C[(int64_t)c * r + i] = i < p ? aug[(int64_t)(r + c) * p + i] : 0.0;
+        for (int i = 0; i < r; ++i) w.C[(int64_t)c * r + i] = i < p ? aug[(int64_t)(r + c) * lda + i] : 0.0;
 }
 
-// Least squares min ||B s - c|| for the columns of R_A listed in idx[0..q-1]
-// (Householder QR in `a` (r x q) and `rhs` (r)); writes s into sol[idx[.]].
-__device__ void ls_passive(const double* RA, int r, const double* c, const int* idx, int q, double* a, double* rhs,
-                           double* sol) {
-    for (int jj = 0; jj < q; ++jj)
-        for (int i = 0; i < r; ++i) a[jj * r + i] = RA[(int64_t)idx[jj] * r + i];
-    for (int i = 0; i < r; ++i) rhs[i] = c[i];
-    for (int j = 0; j < q; ++j) {
-        double sigma = 0.0;
-        for (int i = j + 1; i < r; ++i) sigma += a[j * r + i] * a[j * r + i];
-        const double alpha = a[j * r + j];
-        if (sigma == 0.0) continue;
-        const double nrm = __builtin_sqrt(alpha * alpha + sigma);
-        const double beta = alpha >= 0.0 ? -nrm : nrm;
-        const double tau = (beta - alpha) / beta;
-        const double sc = 1.0 / (alpha - beta);
-        for (int i = j + 1; i < r; ++i) a[j * r + i] *= sc;     // v = [1; a(j+1:, j)]
-        for (int cc = j + 1; cc < q; ++cc) {
-            double d = a[cc * r + j];
-            for (int i = j + 1; i < r; ++i) d += a[j * r + i] * a[cc * r + i];
-            d *= tau;
-            a[cc * r + j] -= d;
-            for (int i = j + 1; i < r; ++i) a[cc * r + i] -= d * a[j * r + i];
-        }
-        double d = rhs[j];
-        for (int i = j + 1; i < r; ++i) d += a[j * r + i] * rhs[i];
-        d *= tau;
-        rhs[j] -= d;
-        for (int i = j + 1; i < r; ++i) rhs[i] -= d * a[j * r + i];
-        a[j * r + j] = beta;
-    }
-    for (int j = q - 1; j >= 0; --j) {
-        double s = rhs[j];
-        for (int cc = j + 1; cc < q; ++cc) s -= a[cc * r + j] * sol[idx[cc]];
-        sol[idx[j]] = s / a[j * r + j];
-    }
+// Leading dimension of the LDS matrices of nnls_solve_kernel: odd, so that a
+// lane-strided column walk of FP64 entries is free of bank conflicts.
+__host__ __device__ constexpr int nnls_ld(int r) { return r | 1; }
+
+__host__ __device__ constexpr size_t nnls_solve_lds(int r) {
+    return ((size_t)(2 * r + 1) * nnls_ld(r) + 3 * 64 + 32) * sizeof(double);
 }
 
+// Stage 2: one wave per column i of M, lane q holding entry q of x, of the
+// gradient, of the subproblem's solution and whether q is in the passive set
+// (r <= 64).  R_A and the subproblem live in LDS.  The subproblem
+// min ||R_A(:, P) s - c|| is factored by Householder steps on the passive
+// columns with c appended as one more column, lane j' owning column j'.
+// Column j of R_A(:, P) is R_A(:, P[j]), zero below row P[j]; the reflections
+// of the earlier columns touch rows up to P[j'] < P[j] only, so it stays zero
+// there and step j runs over rows j .. P[j] (the other terms are exact zeros).
 __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                         const int* __restrict__ K, int r, NnlsWork w, double* H,
                                                         int ldh, double* resid2, int* info) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    extern __shared__ double lds[];
+    const int i = blockIdx.x;
+    const int L = (int)threadIdx.x;
+    const bool lane_ok = L < r;
     if (w.skip != nullptr && w.skip[0] != 0) return;
     if (w.anorm1[1] != 0.0) {                  // invalid K: no solve, NaN results
-        for (int q = 0; q < r; ++q) H[(int64_t)i * ldh + q] = __builtin_nan("");
-        if (resid2 != nullptr) resid2[i] = __builtin_nan("");
-        if (info != nullptr) info[i] = 2;
+        if (lane_ok) H[(int64_t)i * ldh + L] = __builtin_nan("");
+        if (L == 0) {
+            if (resid2 != nullptr) resid2[i] = __builtin_nan("");
+            if (info != nullptr) info[i] = 2;
+        }
         return;
     }
-    const double* RA = w.RA;
-    const double* c = w.C + (int64_t)i * r;
-    double* x = w.scratch + (int64_t)i * (r * r + 6 * r);
-    double* s = x + r;
-    double* g = s + r;
-    double* pass = g + r;          // 1.0 when in the passive set
-    int* idx = (int*)(pass + r);   // passive indices (r ints fit in r doubles)
-    double* rhs = pass + 2 * r;
-    double* a = rhs + r;
+    const int ld = nnls_ld(r);
+    double* sRA = lds;                        // R_A, column u at sRA + u ld
+    double* sa = sRA + r * ld;                // subproblem: passive columns of R_A, then c
+    double* sv = sa + (r + 1) * ld;           // Householder vector of the current step
+    double* sx = sv + 64;                     // x, then c - R_A x, for the gradient
+    double* se = sx + 64;
+    int* sidx = (int*)(se + 64);              // passive indices, ascending
+    for (int u = 0; u < r; ++u)
+        if (lane_ok) sRA[u * ld + L] = w.RA[(int64_t)u * r + L];
+    const double cq = lane_ok ? w.C[(int64_t)i * r + L] : 0.0;
     const int maxit = 3 * r;
     const double tol = 10.0 * DBL_EPSILON * (*w.anorm1) * (double)(p > r ? p : r);
-    for (int q = 0; q < r; ++q) { x[q] = 0.0; pass[q] = 0.0; }
+    const unsigned long long below = (1ull << L) - 1;   // lanes under this one
+    double x = 0.0;
+    bool pass = false;
     int inf = 0, outer = 0;
+    __syncthreads();
     while (true) {
         // g = R_A^T (c - R_A x)
-        for (int q = 0; q < r; ++q) {
-            double e = c[q];
-            for (int u = q; u < r; ++u) e -= RA[(int64_t)u * r + q] * x[u];
-            s[q] = e;                                  // residual, reused below
+        sx[L] = x;
+        __syncthreads();
+        double e = cq;
+#pragma unroll 4
+        for (int u = 0; u < r; ++u)
+            if (lane_ok && u >= L) e -= sRA[u * ld + L] * sx[u];
+        se[L] = e;
+        __syncthreads();
+        double g = 0.0;
+#pragma unroll 4
+        for (int u = 0; u < r; ++u)
+            if (lane_ok && u <= L) g += sRA[L * ld + u] * se[u];
+        // entering index: the largest gradient outside P, when above tol
+        const bool enter = lane_ok && !pass && g > tol;
+        const int tbest = wave_argmax(enter ? g : -INFINITY, enter ? L : 64);
+        if (tbest >= 64) break;
+        if (outer >= maxit) {
+            inf = 1;
+            break;
         }
-        for (int q = 0; q < r; ++q) {
-            double d = 0.0;
-            for (int u = 0; u <= q; ++u) d += RA[(int64_t)q * r + u] * s[u];
-            g[q] = d;
-        }
-        int tbest = -1;
-        double gbest = -DBL_MAX;
-        for (int q = 0; q < r; ++q)
-            if (pass[q] == 0.0 && g[q] > gbest) { gbest = g[q]; tbest = q; }
-        if (tbest < 0 || !(gbest > tol)) break;
-        if (outer >= maxit) { inf = 1; break; }
         ++outer;
-        pass[tbest] = 1.0;
+        if (L == tbest) pass = true;
         int inner = 0;
         while (true) {
-            int qn = 0;
-            for (int q = 0; q < r; ++q)
-                if (pass[q] != 0.0) idx[qn++] = q;
-            for (int q = 0; q < r; ++q) s[q] = 0.0;
-            ls_passive(RA, r, c, idx, qn, a, rhs, s);
-            bool allpos = true;
-            for (int q = 0; q < qn; ++q) allpos = allpos && s[idx[q]] > 0.0;
-            if (allpos) {
-                for (int q = 0; q < r; ++q) x[q] = s[q];
+            const unsigned long long pm = __ballot(pass);
+            const int qn = __popcll(pm);
+            const int pos = __popcll(pm & below);      // this lane's place in P
+            if (pass) sidx[pos] = L;
+            __syncthreads();
+            for (int j = 0; j < qn; ++j)
+                if (lane_ok) sa[j * ld + L] = sRA[sidx[j] * ld + L];
+            if (lane_ok) sa[qn * ld + L] = cq;
+            __syncthreads();
+            for (int j = 0; j < qn; ++j) {
+                const int hi = sidx[j];                // last row that can be nonzero in column j
+                double* colj = sa + j * ld;
+                const double aij = (L > j && L <= hi) ? colj[L] : 0.0;
+                const double sigma = wave_sum(aij * aij);
+                const double alpha = colj[j];
+                if (sigma == 0.0) continue;            // wave-uniform
+                const double nrm = __builtin_sqrt(alpha * alpha + sigma);
+                const double beta = alpha >= 0.0 ? -nrm : nrm;
+                const double tau = (beta - alpha) / beta;
+                const double sc = 1.0 / (alpha - beta);
+                if (L > j && L <= hi) {                // v = [1; a(j+1 .. hi, j) sc]
+                    const double v = aij * sc;
+                    colj[L] = v;
+                    sv[L] = v;
+                }
+                __syncthreads();
+                if (L > j && L <= qn) {                // the later columns and c
+                    double* cc = sa + L * ld;
+                    double d = cc[j];
+#pragma unroll 4
+                    for (int u = j + 1; u <= hi; ++u) d += sv[u] * cc[u];
+                    d *= tau;
+                    cc[j] -= d;
+#pragma unroll 4
+                    for (int u = j + 1; u <= hi; ++u) cc[u] -= d * sv[u];
+                }
+                if (L == j) colj[j] = beta;
+                __syncthreads();
+            }
+            // back substitution, one column of the triangle per step
+            double acc = L < qn ? sa[qn * ld + L] : 0.0;
+            double sol = 0.0;
+            for (int c = qn - 1; c >= 0; --c) {
+                const double sc = lane_value(acc, c) / sa[c * ld + c];
+                if (L == c) sol = sc;
+                if (L < c) acc -= sa[c * ld + L] * sc;
+            }
+            const double sp = __shfl(sol, pos);        // solution entry of index L
+            const double s = pass ? sp : 0.0;
+            if (__ballot(pass && !(s > 0.0)) == 0) {  // all of P positive: accept
+                x = s;
                 break;
             }
-            // Largest step keeping x >= 0 over the indices with s <= 0.  An
+            // Largest step keeping x >= 0 over the indices of P with s <= 0.  An
             // index already at zero (x = 0) allows no step: its ratio is 0,
             // not 0 / 0.  The index that limits the step is set to zero and
-            // leaves P, so this loop ends within qn rounds.
-            double alpha = DBL_MAX;
-            int ubest = -1;
-            for (int q = 0; q < qn; ++q) {
-                const int u = idx[q];
-                if (s[u] <= 0.0) {
-                    const double al = x[u] > 0.0 ? x[u] / (x[u] - s[u]) : 0.0;
-                    if (al < alpha) { alpha = al; ubest = u; }
-                }
-            }
-            if (ubest < 0) {                 // no finite step (NaN in the subproblem)
+            // leaves P, so this loop ends within |P| rounds.
+            const bool lim = pass && s <= 0.0;
+            const double al = lim ? (x > 0.0 ? x / (x - s) : 0.0) : 0.0;
+            const int ubest = wave_argmax(lim ? -al : -INFINITY, lim ? L : 64);
+            if (ubest >= 64) {                         // no finite step (NaN in the subproblem)
                 inf = 1;
                 break;
             }
-            for (int q = 0; q < r; ++q) x[q] += alpha * (s[q] - x[q]);
-            x[ubest] = 0.0;
-            int left = 0;
-            for (int q = 0; q < r; ++q) {
-                if (pass[q] != 0.0 && x[q] <= tol) { pass[q] = 0.0; x[q] = 0.0; }
-                left += pass[q] != 0.0;
+            const double step = lane_value(al, ubest);
+            x += step * (s - x);
+            if (L == ubest) x = 0.0;
+            if (pass && x <= tol) {
+                pass = false;
+                x = 0.0;
             }
+            const int left = __popcll(__ballot(pass));
             if (left == 0 || ++inner > r) break;
         }
     }
-    for (int q = 0; q < r; ++q) H[(int64_t)i * ldh + q] = x[q];
+    if (lane_ok) H[(int64_t)i * ldh + L] = x;
     if (resid2 != nullptr) {
+        sv[L] = x;
+        __syncthreads();
         double e2 = 0.0;
-        for (int row = 0; row < p; ++row) {
+        for (int row = L; row < p; row += 64) {
             double e = -M[(int64_t)i * ldm + row];
-            for (int q = 0; q < r; ++q) e += M[(int64_t)K[q] * ldm + row] * x[q];
+            for (int q = 0; q < r; ++q) e += M[(int64_t)K[q] * ldm + row] * sv[q];
             e2 += e * e;
         }
-        resid2[i] = e2;
+        e2 = wave_sum(e2);
+        if (L == 0) resid2[i] = e2;
     }
-    if (info != nullptr) info[i] = inf;
+    if (info != nullptr && L == 0) info[i] = inf;
 }
 
 // ---- residual (Sec. 4) --------------------------------------------------------------
@@ -386,15 +504,15 @@ __global__ void __launch_bounds__(kThreads) residual_kernel(const double* __rest
         if (threadIdx.x == 0) *out = __builtin_nan("");
         return;
     }
+    // one thread per entry (i, j), i fastest (p n <= 65536)
     double e2 = 0.0, m2 = 0.0;
-    for (int j = threadIdx.x; j < n; j += kThreads) {
-        for (int i = 0; i < p; ++i) {
-            const double mij = M[(int64_t)j * ldm + i];
-            double e = mij;
-            for (int q = 0; q < r; ++q) e -= M[(int64_t)K[q] * ldm + i] * H[(int64_t)j * ldh + q];
-            e2 += e * e;
-            m2 += mij * mij;
-        }
+    for (int el = threadIdx.x; el < p * n; el += kThreads) {
+        const int j = el / p, i = el - j * p;
+        const double mij = M[(int64_t)j * ldm + i];
+        double e = mij;
+        for (int q = 0; q < r; ++q) e -= M[(int64_t)K[q] * ldm + i] * H[(int64_t)j * ldh + q];
+        e2 += e * e;
+        m2 += mij * mij;
     }
     const double E = block_sum(e2, sv);
     const double T = block_sum(m2, sv);
@@ -472,7 +590,7 @@ __global__ void zero_ints_kernel(int* p, int count) {
 }
 
 size_t nnls_bytes(int p, int n, int r) {
-    return ((size_t)p * (r + n) + (size_t)r * r + (size_t)r * n + 2 + (size_t)n * (r * r + 6 * r)) * 8 + 1024;
+    return ((size_t)p * (r + n) + (size_t)r * r + (size_t)r * n + 2) * 8 + 1024;
 }
 
 NnlsWork nnls_layout(void* base, int p, int n, int r) {
@@ -485,8 +603,6 @@ NnlsWork nnls_layout(void* base, int p, int n, int r) {
     w.C = d;
     d += (size_t)r * n;
     w.anorm1 = d;
-    d += 2;
-    w.scratch = d;
     return w;
 }
 
@@ -494,10 +610,22 @@ int nnls_launch(const double* M, int p, int n, int ldm, const int* K, int r, dou
                 int* info, void* ws, hipStream_t stream, const int* skip = nullptr) {
     NnlsWork w = nnls_layout(ws, p, n, r);
     w.skip = skip;
-    hipLaunchKernelGGL(nnls_qr_kernel, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, K, r, w);
+    if (nnls_aug_in_lds(p, n, r)) {
+        const size_t lds = (size_t)nnls_qr_ld(p, true) * (r + n) * sizeof(double);
+        if (lds > 65536)
+            TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_qr_kernel<true>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(nnls_qr_kernel<true>, dim3(1), dim3(kThreads), lds, stream, M, p, n, ldm, K, r, w);
+    } else {
+        hipLaunchKernelGGL(nnls_qr_kernel<false>, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, K, r, w);
+    }
     TSNMF_LAUNCH_CHECK();
-    hipLaunchKernelGGL(nnls_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, stream, M, p, n, ldm, K, r, w, H, ldh,
-                       resid2, info);
+    const size_t lds = nnls_solve_lds(r);
+    if (lds > 65536)
+        TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(nnls_solve_kernel, dim3(n), dim3(64), lds, stream, M, p, n, ldm, K, r, w, H, ldh, resid2,
+                       info);
     TSNMF_LAUNCH_CHECK();
     return TSNMF_OK;
 }
@@ -507,9 +635,19 @@ int nnls_launch(const double* M, int p, int n, int ldm, const int* K, int r, dou
 int select_spa_impl(const double* M, int p, int n, int ldm, const double* colscale, int r, int* K, double* score,
                     int* info, hipStream_t stream) {
     void* ws = nullptr;
-    if (int st = workspace_get(kTicketBytes + (size_t)p * n * 8, stream, &ws)) return st;
-    hipLaunchKernelGGL(spa_kernel, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, colscale, r, K, score, info,
-                       (double*)((char*)ws + kTicketBytes));
+    if (int st = workspace_get(kTicketBytes + (spa_z_in_lds(p, n) ? 0 : (size_t)p * n * 8), stream, &ws)) return st;
+    double* Zg = (double*)((char*)ws + kTicketBytes);
+    if (spa_z_in_lds(p, n)) {
+        const size_t lds = (size_t)p * (n + 1) * sizeof(double);
+        if (lds > 65536)
+            TSNMF_HIP(hipFuncSetAttribute((const void*)spa_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lds));
+        hipLaunchKernelGGL(spa_kernel<true>, dim3(1), dim3(kThreads), lds, stream, M, p, n, ldm, colscale, r, K,
+                           score, info, Zg);
+    } else {
+        hipLaunchKernelGGL(spa_kernel<false>, dim3(1), dim3(kThreads), (size_t)p * sizeof(double), stream, M, p, n,
+                           ldm, colscale, r, K, score, info, Zg);
+    }
     TSNMF_LAUNCH_CHECK();
     return TSNMF_OK;
 }

@@ -93,7 +93,7 @@ def test_gp_select_fewer_distinct_than_r(lib):
     assert K.cpu().tolist() == [1, 2, -1, -1] and int(info.item()) == 2
 
 
-@pytest.mark.parametrize("p,n,r", [(20, 20, 10), (64, 64, 20), (128, 128, 32)])
+@pytest.mark.parametrize("p,n,r", [(20, 20, 10), (64, 64, 20), (128, 128, 32), (100, 100, 40), (200, 200, 64)])
 def test_nnls_matches_oracle(lib, p, n, r):
     M, K = _separable(p, n, r, 50 + n, noise=5e-2)
     Kt = torch.tensor(K, dtype=torch.int32, device="cuda")
@@ -108,6 +108,27 @@ def test_nnls_matches_oracle(lib, p, n, r):
         assert onnls.kkt_violation(A, M[:, i], H[:, i]) <= 1e-10
     rel = lib.residual(_cuda(M), Kt, torch.from_numpy(H).cuda())
     assert abs(float(rel.item()) - ores.relative_residual(M, K, Ho)) <= 1e-12
+
+
+@pytest.mark.parametrize("p,n,r", [(40, 30, 6), (90, 70, 25), (256, 256, 64)])
+def test_nnls_binding_constraints(lib, p, n, r):
+    """Columns with negative parts along a picked column, so that many entries
+    of H sit on the bound and the step-length logic of Lawson-Hanson runs."""
+    M, K = _separable(p, n, r, 70 + r, noise=1e-1)
+    W = M[:, K]
+    M[:, ::3] -= 0.4 * W[:, [0]]
+    M[:, 1::4] -= 0.2 * W[:, [r - 1]]
+    Kt = torch.tensor(K, dtype=torch.int32, device="cuda")
+    H, res, info = lib.nnls(_cuda(M), Kt)
+    H = H.cpu().numpy()
+    Ho, ro, io = onnls.nnls_matrix(M, K)
+    assert (Ho == 0.0).sum() >= n // 3                      # constraints bind
+    assert np.abs(H - Ho).max() <= 1e-8 * max(1.0, np.abs(Ho).max())
+    assert np.allclose(res.cpu().numpy(), ro, rtol=1e-8, atol=1e-20)
+    assert info.cpu().tolist() == io.tolist()
+    A = M[:, K]
+    for i in range(0, n, 5):
+        assert onnls.kkt_violation(A, M[:, i], H[:, i]) <= 1e-10
 
 
 def test_nnls_reduced_equals_full(lib):

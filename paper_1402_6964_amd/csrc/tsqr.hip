@@ -17,6 +17,7 @@ hipError_t launch_small_f64_row(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f64_col(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f32w_row(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_small_f32w_col(int n, const StreamArgs& a, hipStream_t s);
+hipError_t launch_coop_leaf_f64(int n, const StreamArgs& a, hipStream_t s);
 hipError_t launch_wide_f32_row(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f32_col(const WideArgs& a, hipStream_t s);
 hipError_t launch_wide_f64_row(const WideArgs& a, hipStream_t s);
@@ -44,6 +45,10 @@ hipError_t launch_small_kron(int q, const StreamArgs& a, hipStream_t s);
 namespace {
 
 constexpr int kTargetStreams = 2048;   // 256 CUs x 8 resident waves
+// Short FP64 slabs (more than one block, at most 8 x 128 rows), when there
+// are at most one per CU: eight waves per slab (tsqr_coop_leaf.hpp).
+constexpr int64_t kCoopLeafRows = 1024;
+constexpr int64_t kCoopLeafMaxSlabs = 256;
 
 enum class Path { F32, F64, F32W };
 
@@ -91,6 +96,7 @@ struct Plan {
     Path path;
     bool wide;
     bool wy;         // blocked compact-WY leaf (FP32 blocks, 33..64 columns)
+    bool coop_leaf;  // eight waves per short FP64 slab
     int waves;       // waves per slab
     int load;
     int64_t block_rows;
@@ -160,6 +166,11 @@ Plan make_plan(int64_t m, int n, int64_t ld, uint32_t flags, const tsnmf_tsqr_co
     p.streams = (m + p.slab - 1) / p.slab;
     // the FP32 staged loads address a slab through a 32-bit byte range
     if (p.load == LOAD_ROW_STAGED && p.path == Path::F32 && p.slab * n * 4 > kMaxBufSlabBytes) p.load = LOAD_ROW;
+    // few short FP64 slabs (a 1,000-row leaf): each slab is one block of the
+    // eight waves of a workgroup, n dependent steps instead of n per block
+    // (100,000 x 20 in 1,000-row leaves: 93 us for the one-wave leaves)
+    p.coop_leaf = p.path == Path::F64 && !p.wide && !col && p.slab > p.block_rows && p.slab <= kCoopLeafRows &&
+                  p.streams <= kCoopLeafMaxSlabs;
     return p;
 }
 
@@ -301,6 +312,8 @@ int tsqr_r_impl(const void* X, int64_t m, int n, int64_t ld, uint32_t flags, dou
         TSNMF_HIP(p.load == LOAD_COL ? launch_wy_f32_col(aw, stream) : launch_wy_f32_row(aw, stream));
     } else if (p.wide) {
         TSNMF_HIP(launch_wide(p.path, p.load, aw, stream));
+    } else if (p.coop_leaf) {
+        TSNMF_HIP(launch_coop_leaf_f64(n, a, stream));
     } else {
         TSNMF_HIP(launch_leaf(p.path, p.load, n, a, stream));
     }

@@ -109,6 +109,28 @@ def test_plain_fp64_config(lib):
     assert np.abs(csg - d1).max() / d1.max() <= 1e-13
 
 
+@pytest.mark.parametrize("n,leaf,m,layout,arity", [
+    (1, 1000, 100_003, "row", 0), (7, 777, 60_001, "padded", 2), (13, 1000, 255_999, "row", 0),
+    (13, 1000, 256_001, "row", 0), (20, 1024, 200_000, "padded", 0), (20, 1000, 100_000, "col", 2),
+    (32, 300, 50_000, "row", 2), (32, 1024, 1_000, "row", 0)])
+def test_fp64_short_slabs(lib, n, leaf, m, layout, arity):
+    """FP64 slabs of one to eight blocks (at most 1,024 rows), at most 256 of
+    them: the eight waves of a workgroup factor each slab as one block.  257
+    slabs, column-major input and single-block slabs take the one-wave leaf;
+    every case against the oracle run with the same leaves, ragged last
+    slabs included."""
+    X, _ = _layout_view(None, m, n, layout, torch.float64, 700 + n)
+    cfg = lib.TsqrConfig(leaf_rows=leaf, tree_arity=arity, rows_per_lane=0)
+    Rg, csg = _run(lib, X, config=cfg)
+    X64 = X.cpu().numpy().astype(np.float64)
+    Ro = otsqr.tsqr_r_final(X64, leaf_rows=leaf)
+    assert np.all(np.tril(Rg, -1) == 0.0) and np.all(np.diag(Rg) >= 0.0)
+    assert np.abs(Rg - Ro).max() / np.abs(Ro).max() <= 1e-11
+    assert _rel_gram(Rg, X64) <= 1e-12
+    d = np.abs(X64).sum(axis=0)
+    assert np.abs(csg - d).max() / d.max() <= 1e-13
+
+
 def test_fp32_input_fp64_leaves(lib):
     """TSNMF_LEAF_F64: FP32 bytes widened exactly, FP64 throughout."""
     X = synth.random_matrix(90_001, 17, dtype=torch.float32, seed_tag=5, dist="lognormal")

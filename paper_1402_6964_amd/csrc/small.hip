@@ -409,12 +409,14 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
             const int pos = __popcll(pm & below);      // this lane's place in P
             if (pass) sidx[pos] = L;
             __syncthreads();
+#pragma unroll 4
             for (int j = 0; j < qn; ++j)
                 if (lane_ok) sa[j * ld + L] = sRA[sidx[j] * ld + L];
             if (lane_ok) sa[qn * ld + L] = cq;
             __syncthreads();
             for (int j = 0; j < qn; ++j) {
                 const int hi = sidx[j];                // last row that can be nonzero in column j
+                if (hi == j) continue;                 // zero below the diagonal: sigma = 0, no step
                 double* colj = sa + j * ld;
                 const double aij = (L > j && L <= hi) ? colj[L] : 0.0;
                 const double sigma = wave_sum(aij * aij);

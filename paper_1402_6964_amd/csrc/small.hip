@@ -524,24 +524,45 @@ __global__ void __launch_bounds__(kThreads) residual_kernel(const double* __rest
 // ---- greedy XRAY (Sec. 2.1) -------------------------------------------------------
 // One pick: score_j = ||Res^T M(:, j)|| / ||M(:, j)|| over unpicked columns with
 // ||M(:, j)|| > 0 (Res = M before the first pick), argmax, append to K.
+// With XL, M (ld p | 1, odd: conflict-free column walks) and Res are read
+// from LDS copies; every sum keeps the order of the global version.
+__host__ __device__ constexpr bool xray_in_lds(int p, int n) {
+    return (size_t)((p | 1) + p) * n * sizeof(double) <= kLdsCap;
+}
+template <bool XL>
 __global__ void __launch_bounds__(kThreads) xray_pick_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                              const double* __restrict__ Res, int t, int* K,
                                                              int* state) {
-    __shared__ double sv[kThreads];
-    __shared__ int si[kThreads];
-    if (state[0] != 0) return;                       // stopped earlier
+    extern __shared__ double xr_lds[];
+    __shared__ double sv[kThreads / 64];
+    __shared__ int si[kThreads / 64];
+    if (state[0] != 0) return;                       // stopped earlier (uniform)
+    const int lm = XL ? (p | 1) : ldm;
+    const double* Mm = XL ? (const double*)xr_lds : M;
+    const double* Rr = XL ? (const double*)(xr_lds + (size_t)lm * n) : Res;
+    if constexpr (XL) {
+        for (int e = threadIdx.x; e < p * n; e += kThreads) {
+            const int c = e / p, i = e - c * p;
+            xr_lds[c * lm + i] = M[(int64_t)c * ldm + i];
+            xr_lds[(size_t)lm * n + e] = Res[e];
+        }
+        __syncthreads();
+    }
     const int j = threadIdx.x;
     double score = -DBL_MAX;
     if (j < n) {
         bool used = false;
         for (int q = 0; q < t; ++q) used = used || K[q] == j;
+        const double* mj = Mm + (int64_t)j * lm;
         double mn = 0.0;
-        for (int i = 0; i < p; ++i) mn += M[(int64_t)j * ldm + i] * M[(int64_t)j * ldm + i];
+        for (int i = 0; i < p; ++i) mn += mj[i] * mj[i];
         if (!used && mn > 0.0) {
             double s2 = 0.0;
             for (int c = 0; c < n; ++c) {
+                const double* rc = Rr + (int64_t)c * p;
                 double d = 0.0;
-                for (int i = 0; i < p; ++i) d += Res[(int64_t)c * p + i] * M[(int64_t)j * ldm + i];
+#pragma unroll 4
+                for (int i = 0; i < p; ++i) d += rc[i] * mj[i];
                 s2 += d * d;
             }
             score = __builtin_sqrt(s2) / __builtin_sqrt(mn);
@@ -689,11 +710,21 @@ int select_xray_impl(const double* M, int p, int n, int ldm, int r, int* K, int*
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, state, 2);
     TSNMF_LAUNCH_CHECK();
     const int64_t pn = (int64_t)p * n;
+    const bool xl = xray_in_lds(p, n);
+    const size_t xl_lds = (size_t)((p | 1) + p) * n * sizeof(double);
+    if (xl && xl_lds > 65536)
+        TSNMF_HIP(hipFuncSetAttribute((const void*)xray_pick_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)xl_lds));
     hipLaunchKernelGGL(copy_matrix_kernel, dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, stream, M, p, n, ldm,
                        Res);
     TSNMF_LAUNCH_CHECK();
     for (int t = 0; t < r && t < n; ++t) {
-        hipLaunchKernelGGL(xray_pick_kernel, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, Res, t, K, state);
+        if (xl)
+            hipLaunchKernelGGL(xray_pick_kernel<true>, dim3(1), dim3(kThreads), xl_lds, stream, M, p, n, ldm, Res, t, K,
+                               state);
+        else
+            hipLaunchKernelGGL(xray_pick_kernel<false>, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, Res, t, K,
+                               state);
         TSNMF_LAUNCH_CHECK();
         if (t + 1 == r) break;
         // H = NNLS(M(:, K[0..t]), M) and the new residual; both do nothing on the

@@ -376,11 +376,37 @@ def extras(torch, tsnmf, synth, dev, check=True, tuned=None):
         pipeline(gs.cuda_stream)
     gp_.replay()
     tg = _timed(torch, gp_.replay, 20)
+    # the other n x n selections on the same R: greedy XRAY (r picks, an NNLS
+    # fit after each) and the residual curve of SPA's picks for ranks 1..r
+    Kx = torch.empty(r, dtype=torch.int32, device=dev)
+    infx = torch.empty(1, dtype=torch.int32, device=dev)
+    Ks = torch.empty(r, dtype=torch.int32, device=dev)
+    Hs = torch.empty((n, r), dtype=torch.float64, device=dev)
+    curve = torch.empty(r, dtype=torch.float64, device=dev)
+    infs = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def xray():
+        st = tsnmf.tsnmf_select_xray(R, n, n, n, r, Kx, infx, stream)
+        if st != 0:
+            raise tsnmf.TsnmfError("tsnmf_select_xray", st)
+
+    def sweep():
+        st = tsnmf.tsnmf_rank_sweep(R, n, n, n, cs1, r, Ks, Hs, r, curve, infs, stream)
+        if st != 0:
+            raise tsnmf.TsnmfError("tsnmf_rank_sweep", st)
+
+    xray()
+    sweep()
+    tx = _timed(torch, xray, 20)
+    tsw = _timed(torch, sweep, 20)
     out["plain_fp64"] = {"workload": "100,000 x 20 FP64 row-major", "tsqr_ms": round(t * 1e3, 4),
                          "tsqr_gbs": round(m * n * 8 / t / 1e9, 1),
                          "pipeline": "TSQR (1,000-row leaves, binary tree) -> SPA (r = 10) -> NNLS -> residual",
                          "pipeline_us": round(tp * 1e6, 1), "pipeline_graph_us": round(tg * 1e6, 1),
-                         "K": sorted(K.cpu().tolist()), "K_planted": d["K"], "residual": float(rel.item())}
+                         "K": sorted(K.cpu().tolist()), "K_planted": d["K"], "residual": float(rel.item()),
+                         "xray_us": round(tx * 1e6, 1), "K_xray": sorted(Kx.cpu().tolist()),
+                         "rank_sweep_us": round(tsw * 1e6, 1),
+                         "residual_curve": [float("%.4g" % v) for v in curve.cpu().tolist()]}
     del X, d
     torch.cuda.empty_cache()
 

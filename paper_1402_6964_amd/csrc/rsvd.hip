@@ -161,17 +161,4 @@ int rsvd_impl(const double* R, int n, int ldr, double* S, double* V, int ldv, do
     return TSNMF_OK;
 }
 
-int rank_sweep_impl(const double* R, int p, int n, int ldr, const double* colscale, int rmax, int* K, double* H,
-                    int ldh, double* resid, int* info, hipStream_t stream) {
-    // SPA's picks for rmax are nested: the first r of them are SPA's picks
-    // for r.  If SPA stops early, K holds -1 past its picks and the NNLS of
-    // those prefixes reports NaN.
-    if (int st = select_spa_impl(R, p, n, ldr, colscale, rmax, K, nullptr, info, stream)) return st;
-    for (int r = 1; r <= rmax; ++r) {
-        if (int st = nnls_impl(R, p, n, ldr, K, r, H, ldh, nullptr, nullptr, stream)) return st;
-        if (int st = residual_impl(R, p, n, ldr, K, r, H, ldh, resid + (r - 1), stream)) return st;
-    }
-    return TSNMF_OK;
-}
-
 }  // namespace tsnmf

@@ -238,8 +238,12 @@ struct NnlsWork {
     double* aug;      // p x (r + n) column-major: [A | M]
     double* RA;       // r x r column-major
     double* C;        // r x n column-major
-    double* anorm1;   // ||A||_1; the next slot is 1.0 when K holds an index outside [0, n)
+    double* anorm1;   // [0] ||A||_1, [1] 1.0 when K holds an index outside [0, n),
+                      // [2] (prefix mode) the number of leading valid indices,
+                      // then the l1 norm of every column of A
     const int* skip;  // when non-null and nonzero, do nothing (XRAY after an early stop)
+    int prefix;       // factor the leading valid columns only (the rank sweep: every
+                      // prefix K[0..r) shares the first r Householder steps)
 };
 
 // 1 when some K[q] (q < r) is outside [0, n).  Checked before any access that
@@ -262,27 +266,39 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     extern __shared__ double qr_lds[];
     __shared__ double sv[kThreads];
     __shared__ double v[256];
-    __shared__ int badk;
+    __shared__ int badk, rvs;
     const int t = threadIdx.x;
     const int lda = nnls_qr_ld(p, AL);
     if (w.skip != nullptr && w.skip[0] != 0) return;
     if (t == 0) {
-        badk = bad_indices(K, r, n);
+        if (w.prefix) {
+            int rv = 0;
+            while (rv < r && K[rv] >= 0 && K[rv] < n) ++rv;
+            badk = 0;
+            rvs = rv;
+            w.anorm1[2] = (double)rv;
+        } else {
+            badk = bad_indices(K, r, n);
+            rvs = r;
+        }
         w.anorm1[1] = badk ? 1.0 : 0.0;
     }
     __syncthreads();
     if (badk) return;
+    const int rv = rvs;                      // columns of A taken from M; the rest are zero
     const int ncol = r + n;
     double* aug = AL ? qr_lds : w.aug;
+    double* cn1 = w.anorm1 + 3;
     for (int c = t; c < ncol; c += kThreads) {
-        const int src = c < r ? K[c] : c - r;
-        for (int i = 0; i < p; ++i) aug[(int64_t)c * lda + i] = M[(int64_t)src * ldm + i];
+        const int src = c < r ? (c < rv ? K[c] : -1) : c - r;
+        for (int i = 0; i < p; ++i) aug[(int64_t)c * lda + i] = src >= 0 ? M[(int64_t)src * ldm + i] : 0.0;
     }
-    // ||A||_1 = largest column l1 norm of A
+    // ||A||_1 = largest column l1 norm of A (each column's kept for the prefixes)
     double a1 = 0.0;
     for (int c = t; c < r; c += kThreads) {
         double s = 0.0;
         for (int i = 0; i < p; ++i) s += __builtin_fabs(aug[(int64_t)c * lda + i]);
+        cn1[c] = s;
         a1 = s > a1 ? s : a1;
     }
     sv[t] = a1;
@@ -293,7 +309,7 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     }
     if (t == 0) *w.anorm1 = sv[0];
     __syncthreads();
-    for (int j = 0; j < r && j < p; ++j) {
+    for (int j = 0; j < rv && j < p; ++j) {
         double* col = aug + (int64_t)j * lda;
         double part = 0.0;
         for (int i = j + 1 + t; i < p; i += kThreads) part = __builtin_fma(col[i], col[i], part);
@@ -345,22 +361,17 @@ __host__ __device__ constexpr size_t nnls_solve_lds(int r) {
 // Column j of R_A(:, P) is R_A(:, P[j]), zero below row P[j]; the reflections
 // of the earlier columns touch rows up to P[j'] < P[j] only, so it stays zero
 // there and step j runs over rows j .. P[j] (the other terms are exact zeros).
-__global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict__ M, int p, int n, int ldm,
-                                                        const int* __restrict__ K, int r, NnlsWork w, double* H,
-                                                        int ldh, double* resid2, int* info) {
-    extern __shared__ double lds[];
-    const int i = blockIdx.x;
+// Column i of M: R_A is the leading r x r block of `RA` and c the first r
+// entries of `ci` (column-major, leading dimension ldra); `lds` holds at least
+// nnls_solve_lds(r) bytes.  Writes x to h (when non-null), ||M(:, K) x - M(:, i)||^2
+// to *resid2 and the iteration-cap flag to *info (when non-null).
+__device__ __forceinline__ void nnls_solve_wave(const double* __restrict__ M, int p, int ldm,
+                                                const int* __restrict__ K, int r, int ldra,
+                                                const double* __restrict__ RA, const double* __restrict__ ci,
+                                                double tol, double* lds, int i, double* h, double* resid2,
+                                                int* info) {
     const int L = (int)threadIdx.x;
     const bool lane_ok = L < r;
-    if (w.skip != nullptr && w.skip[0] != 0) return;
-    if (w.anorm1[1] != 0.0) {                  // invalid K: no solve, NaN results
-        if (lane_ok) H[(int64_t)i * ldh + L] = __builtin_nan("");
-        if (L == 0) {
-            if (resid2 != nullptr) resid2[i] = __builtin_nan("");
-            if (info != nullptr) info[i] = 2;
-        }
-        return;
-    }
     const int ld = nnls_ld(r);
     double* sRA = lds;                        // R_A, column u at sRA + u ld
     double* sa = sRA + r * ld;                // subproblem: passive columns of R_A, then c
@@ -369,10 +380,9 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
     double* se = sx + 64;
     int* sidx = (int*)(se + 64);              // passive indices, ascending
     for (int u = 0; u < r; ++u)
-        if (lane_ok) sRA[u * ld + L] = w.RA[(int64_t)u * r + L];
-    const double cq = lane_ok ? w.C[(int64_t)i * r + L] : 0.0;
+        if (lane_ok) sRA[u * ld + L] = RA[(int64_t)u * ldra + L];
+    const double cq = lane_ok ? ci[L] : 0.0;
     const int maxit = 3 * r;
-    const double tol = 10.0 * DBL_EPSILON * (*w.anorm1) * (double)(p > r ? p : r);
     const unsigned long long below = (1ull << L) - 1;   // lanes under this one
     double x = 0.0;
     bool pass = false;
@@ -481,7 +491,7 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
             if (left == 0 || ++inner > r) break;
         }
     }
-    if (lane_ok) H[(int64_t)i * ldh + L] = x;
+    if (lane_ok && h != nullptr) h[L] = x;
     if (resid2 != nullptr) {
         sv[L] = x;
         __syncthreads();
@@ -492,9 +502,75 @@ __global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict
             e2 += e * e;
         }
         e2 = wave_sum(e2);
-        if (L == 0) resid2[i] = e2;
+        if (L == 0) *resid2 = e2;
     }
-    if (info != nullptr && L == 0) info[i] = inf;
+    if (info != nullptr && L == 0) *info = inf;
+}
+
+__global__ void __launch_bounds__(64) nnls_solve_kernel(const double* __restrict__ M, int p, int n, int ldm,
+                                                        const int* __restrict__ K, int r, NnlsWork w, double* H,
+                                                        int ldh, double* resid2, int* info) {
+    extern __shared__ double lds[];
+    const int i = blockIdx.x;
+    const int L = (int)threadIdx.x;
+    if (w.skip != nullptr && w.skip[0] != 0) return;
+    if (w.anorm1[1] != 0.0) {                  // invalid K: no solve, NaN results
+        if (L < r) H[(int64_t)i * ldh + L] = __builtin_nan("");
+        if (L == 0) {
+            if (resid2 != nullptr) resid2[i] = __builtin_nan("");
+            if (info != nullptr) info[i] = 2;
+        }
+        return;
+    }
+    const double tol = 10.0 * DBL_EPSILON * (*w.anorm1) * (double)(p > r ? p : r);
+    nnls_solve_wave(M, p, ldm, K, r, r, w.RA, w.C + (int64_t)i * r, tol, lds, i, H + (int64_t)i * ldh,
+                    resid2 != nullptr ? resid2 + i : nullptr, info != nullptr ? info + i : nullptr);
+}
+
+// Rank sweep: workgroup (i, r - 1) solves column i on the prefix K[0..r) with
+// R_A and C of the rmax-column QR in prefix mode (their leading r x r block and
+// first r rows are exactly the factors of that prefix) and the tolerance from
+// the prefix's ||A||_1; e2[(r - 1) n + i] gets the squared residual of the
+// column (NaN past the valid prefix), H the fit at rmax.
+__global__ void __launch_bounds__(64) sweep_solve_kernel(const double* __restrict__ M, int p, int n, int ldm,
+                                                         const int* __restrict__ K, int rmax, NnlsWork w, double* H,
+                                                         int ldh, double* e2) {
+    extern __shared__ double lds[];
+    const int i = blockIdx.x;
+    const int r = (int)blockIdx.y + 1;
+    const int L = (int)threadIdx.x;
+    double* out = e2 + (int64_t)(r - 1) * n + i;
+    if (r > (int)w.anorm1[2]) {                // past SPA's picks
+        if (L == 0) *out = __builtin_nan("");
+        if (r == rmax && L < rmax) H[(int64_t)i * ldh + L] = __builtin_nan("");
+        return;
+    }
+    const double* cn1 = w.anorm1 + 3;
+    double a1 = 0.0;
+    for (int c = 0; c < r; ++c) a1 = cn1[c] > a1 ? cn1[c] : a1;
+    const double tol = 10.0 * DBL_EPSILON * a1 * (double)(p > r ? p : r);
+    nnls_solve_wave(M, p, ldm, K, r, rmax, w.RA, w.C + (int64_t)i * rmax, tol, lds, i,
+                    r == rmax ? H + (int64_t)i * ldh : nullptr, out, nullptr);
+}
+
+// resid[r - 1] = sum_i e2[(r - 1) n + i] / ||M||_F^2 (0 when M = 0; NaN past
+// the valid prefix), the relative residual of Sec. 4 for every rank.
+__global__ void __launch_bounds__(kThreads) sweep_finish_kernel(const double* __restrict__ M, int p, int n, int ldm,
+                                                                int rmax, const double* __restrict__ e2,
+                                                                double* resid) {
+    __shared__ double sv[kThreads / 64];
+    double m2 = 0.0;
+    for (int el = threadIdx.x; el < p * n; el += kThreads) {
+        const int j = el / p, i = el - j * p;
+        const double mij = M[(int64_t)j * ldm + i];
+        m2 += mij * mij;
+    }
+    const double T = block_sum(m2, sv);
+    for (int r = threadIdx.x; r < rmax; r += kThreads) {
+        double E = 0.0;
+        for (int i = 0; i < n; ++i) E += e2[(int64_t)r * n + i];
+        resid[r] = T > 0.0 ? E / T : (E == E ? 0.0 : E);
+    }
 }
 
 // ---- residual (Sec. 4) --------------------------------------------------------------
@@ -613,7 +689,7 @@ __global__ void zero_ints_kernel(int* p, int count) {
 }
 
 size_t nnls_bytes(int p, int n, int r) {
-    return ((size_t)p * (r + n) + (size_t)r * r + (size_t)r * n + 2) * 8 + 1024;
+    return ((size_t)p * (r + n) + (size_t)r * r + (size_t)r * n + 3 + r) * 8 + 1024;
 }
 
 NnlsWork nnls_layout(void* base, int p, int n, int r) {
@@ -629,10 +705,8 @@ NnlsWork nnls_layout(void* base, int p, int n, int r) {
     return w;
 }
 
-int nnls_launch(const double* M, int p, int n, int ldm, const int* K, int r, double* H, int ldh, double* resid2,
-                int* info, void* ws, hipStream_t stream, const int* skip = nullptr) {
-    NnlsWork w = nnls_layout(ws, p, n, r);
-    w.skip = skip;
+int nnls_qr_launch(const double* M, int p, int n, int ldm, const int* K, int r, const NnlsWork& w,
+                   hipStream_t stream) {
     if (nnls_aug_in_lds(p, n, r)) {
         const size_t lds = (size_t)nnls_qr_ld(p, true) * (r + n) * sizeof(double);
         if (lds > 65536)
@@ -643,6 +717,14 @@ int nnls_launch(const double* M, int p, int n, int ldm, const int* K, int r, dou
         hipLaunchKernelGGL(nnls_qr_kernel<false>, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, K, r, w);
     }
     TSNMF_LAUNCH_CHECK();
+    return TSNMF_OK;
+}
+
+int nnls_launch(const double* M, int p, int n, int ldm, const int* K, int r, double* H, int ldh, double* resid2,
+                int* info, void* ws, hipStream_t stream, const int* skip = nullptr) {
+    NnlsWork w = nnls_layout(ws, p, n, r);
+    w.skip = skip;
+    if (int st = nnls_qr_launch(M, p, n, ldm, K, r, w, stream)) return st;
     const size_t lds = nnls_solve_lds(r);
     if (lds > 65536)
         TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -688,6 +770,34 @@ int nnls_impl(const double* M, int p, int n, int ldm, const int* K, int r, doubl
     void* ws = nullptr;
     if (int st = workspace_get(kTicketBytes + nnls_bytes(p, n, r), stream, &ws)) return st;
     return nnls_launch(M, p, n, ldm, K, r, H, ldh, resid2, info, (char*)ws + kTicketBytes, stream);
+}
+
+int rank_sweep_impl(const double* R, int p, int n, int ldr, const double* colscale, int rmax, int* K, double* H,
+                    int ldh, double* resid, int* info, hipStream_t stream) {
+    // SPA's picks for rmax are nested: the first r of them are SPA's picks
+    // for r.  One QR of R(:, K) in prefix mode gives the factors of every
+    // prefix; every (column, rank) pair is then solved in one launch and the
+    // curve summed from the squared column residuals.  If SPA stops early, K
+    // holds -1 past its picks and the ranks past them report NaN.
+    if (int st = select_spa_impl(R, p, n, ldr, colscale, rmax, K, nullptr, info, stream)) return st;
+    const size_t nb = nnls_bytes(p, n, rmax);
+    void* ws = nullptr;
+    if (int st = workspace_get(kTicketBytes + nb + (size_t)rmax * n * 8, stream, &ws)) return st;
+    char* base = (char*)ws + kTicketBytes;
+    NnlsWork w = nnls_layout(base, p, n, rmax);
+    w.prefix = 1;
+    double* e2 = (double*)(base + nb);
+    if (int st = nnls_qr_launch(R, p, n, ldr, K, rmax, w, stream)) return st;
+    const size_t lds = nnls_solve_lds(rmax);
+    if (lds > 65536)
+        TSNMF_HIP(hipFuncSetAttribute((const void*)sweep_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    hipLaunchKernelGGL(sweep_solve_kernel, dim3(n, rmax), dim3(64), lds, stream, R, p, n, ldr, K, rmax, w, H, ldh,
+                       e2);
+    TSNMF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sweep_finish_kernel, dim3(1), dim3(kThreads), 0, stream, R, p, n, ldr, rmax, e2, resid);
+    TSNMF_LAUNCH_CHECK();
+    return TSNMF_OK;
 }
 
 int residual_impl(const double* M, int p, int n, int ldm, const int* K, int r, const double* H, int ldh,

@@ -419,13 +419,15 @@ __device__ __forceinline__ void nnls_solve_wave(const double* __restrict__ M, in
             const int pos = __popcll(pm & below);      // this lane's place in P
             if (pass) sidx[pos] = L;
             __syncthreads();
-#pragma unroll 4
-            for (int j = 0; j < qn; ++j)
-                if (lane_ok) sa[j * ld + L] = sRA[sidx[j] * ld + L];
+            const int pj = sidx[L];                    // P[L] in lanes L < qn (read by every lane)
+            for (int j = 0; j < qn; ++j) {
+                const int src = __builtin_amdgcn_readlane(pj, j);
+                if (lane_ok) sa[j * ld + L] = sRA[src * ld + L];
+            }
             if (lane_ok) sa[qn * ld + L] = cq;
             __syncthreads();
             for (int j = 0; j < qn; ++j) {
-                const int hi = sidx[j];                // last row that can be nonzero in column j
+                const int hi = __builtin_amdgcn_readlane(pj, j);   // last row that can be nonzero in column j
                 if (hi == j) continue;                 // zero below the diagonal: sigma = 0, no step
                 double* colj = sa + j * ld;
                 const double aij = (L > j && L <= hi) ? colj[L] : 0.0;
@@ -456,10 +458,13 @@ __device__ __forceinline__ void nnls_solve_wave(const double* __restrict__ M, in
                 __syncthreads();
             }
             // back substitution, one column of the triangle per step
-            double acc = L < qn ? sa[qn * ld + L] : 0.0;
+            // reciprocals of the diagonal formed together, off the serial chain
+            const int Lq = L < qn ? L : 0;             // in-range index for every lane
+            const double dinv = L < qn ? 1.0 / sa[Lq * ld + Lq] : 0.0;
+            double acc = L < qn ? sa[qn * ld + Lq] : 0.0;
             double sol = 0.0;
             for (int c = qn - 1; c >= 0; --c) {
-                const double sc = lane_value(acc, c) / sa[c * ld + c];
+                const double sc = lane_value(acc, c) * lane_value(dinv, c);
                 if (L == c) sol = sc;
                 if (L < c) acc -= sa[c * ld + L] * sc;
             }

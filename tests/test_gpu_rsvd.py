@@ -163,3 +163,27 @@ def test_rank_sweep_stops_when_the_residual_vanishes(lib):
     r = res.cpu().numpy()
     assert np.allclose(r[:3], reso, rtol=0, atol=1e-15) and r[2] <= 1e-30
     assert np.all(np.isnan(r[3:]))
+
+
+@pytest.mark.parametrize("p,n,rmax", [(20, 20, 10), (64, 64, 32), (200, 200, 64)])
+def test_rank_sweep_equals_one_fit_per_prefix(lib, p, n, rmax):
+    """The sweep factors R(:, K[0..rmax)) once and reads every prefix's factors
+    from it; the same curve from one tsnmf_nnls + tsnmf_residual call per prefix
+    (summation order aside), and the fit at rmax bit for bit."""
+    rng = np.random.default_rng([43, n])
+    W = rng.uniform(size=(p, rmax))
+    Hm = rng.uniform(size=(rmax, n))
+    M = W @ Hm + 0.05 * rng.uniform(size=(p, n))
+    M[:, ::4] -= 0.2 * W[:, [0]]
+    Mg = _cuda(M)
+    K, res, H, info = lib.rank_sweep(Mg, rmax)
+    torch.cuda.synchronize()
+    assert int(info.item()) == rmax
+    curve = res.cpu().numpy()
+    for r in range(1, rmax + 1):
+        Kr = K[:r].contiguous()
+        Hr, _, _ = lib.nnls(Mg, Kr)
+        rel = float(lib.residual(Mg, Kr, Hr).item())
+        assert abs(curve[r - 1] - rel) <= 1e-12 * rel + 1e-300
+        if r == rmax:
+            assert np.array_equal(H.cpu().numpy(), Hr.cpu().numpy())

@@ -260,8 +260,8 @@ __host__ __device__ constexpr int nnls_qr_ld(int p, bool al) { return al ? (p | 
 __host__ __device__ constexpr bool nnls_aug_in_lds(int p, int n, int r) {
     return (size_t)nnls_qr_ld(p, true) * (r + n) * sizeof(double) <= kLdsCap;
 }
-template <bool AL>
-__global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restrict__ M, int p, int n, int ldm,
+template <bool AL, int NT>
+__global__ void __launch_bounds__(NT) nnls_qr_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                            const int* __restrict__ K, int r, NnlsWork w) {
     extern __shared__ double qr_lds[];
     __shared__ double sv[kThreads];
@@ -289,13 +289,13 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     const int ncol = r + n;
     double* aug = AL ? qr_lds : w.aug;
     double* cn1 = w.anorm1 + 3;
-    for (int c = t; c < ncol; c += kThreads) {
+    for (int c = t; c < ncol; c += NT) {
         const int src = c < r ? (c < rv ? K[c] : -1) : c - r;
         for (int i = 0; i < p; ++i) aug[(int64_t)c * lda + i] = src >= 0 ? M[(int64_t)src * ldm + i] : 0.0;
     }
     // ||A||_1 = largest column l1 norm of A (each column's kept for the prefixes)
     double a1 = 0.0;
-    for (int c = t; c < r; c += kThreads) {
+    for (int c = t; c < r; c += NT) {
         double s = 0.0;
         for (int i = 0; i < p; ++i) s += __builtin_fabs(aug[(int64_t)c * lda + i]);
         cn1[c] = s;
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     }
     sv[t] = a1;
     __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (t < s) sv[t] = sv[t] > sv[t + s] ? sv[t] : sv[t + s];
         __syncthreads();
     }
@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
     for (int j = 0; j < rv && j < p; ++j) {
         double* col = aug + (int64_t)j * lda;
         double part = 0.0;
-        for (int i = j + 1 + t; i < p; i += kThreads) part = __builtin_fma(col[i], col[i], part);
-        const double sigma = block_sum(part, sv);
+        for (int i = j + 1 + t; i < p; i += NT) part = __builtin_fma(col[i], col[i], part);
+        const double sigma = NT == 64 ? wave_sum(part) : block_sum(part, sv);
         const double alpha = col[j];
         double beta = alpha, tau = 0.0, sc = 0.0;
         if (sigma != 0.0) {
@@ -322,9 +322,9 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
             tau = (beta - alpha) / beta;
             sc = 1.0 / (alpha - beta);
         }
-        for (int i = j + t; i < p; i += kThreads) v[i] = (i == j) ? 1.0 : col[i] * sc;
+        for (int i = j + t; i < p; i += NT) v[i] = (i == j) ? 1.0 : col[i] * sc;
         __syncthreads();
-        for (int c = j + 1 + t; c < ncol; c += kThreads) {
+        for (int c = j + 1 + t; c < ncol; c += NT) {
             double* cc = aug + (int64_t)c * lda;
             double d = 0.0;
 #pragma unroll 4
@@ -335,13 +335,13 @@ __global__ void __launch_bounds__(kThreads) nnls_qr_kernel(const double* __restr
         }
         __syncthreads();
         if (t == 0) col[j] = beta;
-        for (int i = j + 1 + t; i < p; i += kThreads) col[i] = 0.0;
+        for (int i = j + 1 + t; i < p; i += NT) col[i] = 0.0;
         __syncthreads();
     }
     // R_A (rows beyond p stay zero) and C
-    for (int c = t; c < r; c += kThreads)
+    for (int c = t; c < r; c += NT)
         for (int i = 0; i < r; ++i) w.RA[(int64_t)c * r + i] = (i <= c && i < p) ? aug[(int64_t)c * lda + i] : 0.0;
-    for (int c = t; c < n; c += kThreads)
+    for (int c = t; c < n; c += NT)
         for (int i = 0; i < r; ++i) w.C[(int64_t)c * r + i] = i < p ? aug[(int64_t)(r + c) * lda + i] : 0.0;
 }
 
@@ -712,14 +712,25 @@ NnlsWork nnls_layout(void* base, int p, int n, int r) {
 
 int nnls_qr_launch(const double* M, int p, int n, int ldm, const int* K, int r, const NnlsWork& w,
                    hipStream_t stream) {
+    // one wave when it has few columns per lane (its steps then need no
+    // cross-wave sums or barriers), else kThreads
     if (nnls_aug_in_lds(p, n, r)) {
         const size_t lds = (size_t)nnls_qr_ld(p, true) * (r + n) * sizeof(double);
-        if (lds > 65536)
-            TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_qr_kernel<true>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(nnls_qr_kernel<true>, dim3(1), dim3(kThreads), lds, stream, M, p, n, ldm, K, r, w);
+        if (r + n <= 128) {
+            if (lds > 65536)
+                TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_qr_kernel<true, 64>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((nnls_qr_kernel<true, 64>), dim3(1), dim3(64), lds, stream, M, p, n, ldm, K, r, w);
+        } else {
+            if (lds > 65536)
+                TSNMF_HIP(hipFuncSetAttribute((const void*)nnls_qr_kernel<true, kThreads>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((nnls_qr_kernel<true, kThreads>), dim3(1), dim3(kThreads), lds, stream, M, p, n, ldm,
+                               K, r, w);
+        }
     } else {
-        hipLaunchKernelGGL(nnls_qr_kernel<false>, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, K, r, w);
+        hipLaunchKernelGGL((nnls_qr_kernel<false, kThreads>), dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, K, r,
+                           w);
     }
     TSNMF_LAUNCH_CHECK();
     return TSNMF_OK;

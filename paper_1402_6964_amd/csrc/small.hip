@@ -1,8 +1,9 @@
 // The n x n steps of near-separable NMF on the GPU, in FP64: extreme-column
 // selection (SPA, greedy XRAY, Gaussian-projection selection), the NNLS solve
-// for H and the relative residual.  The paper notes that these run on O(n^2)
-// data and are cheap even in serial (Sec. 2.4); they are single-workgroup or
-// one-thread-per-column kernels, stream-ordered, with no host synchronisation.
+// for H, the relative residual and its curve over ranks.  The paper notes that
+// these run on O(n^2) data and are cheap even in serial (Sec. 2.4); they are
+// single-workgroup kernels (the matrices in LDS when they fit) or one wave per
+// column of H, stream-ordered, with no host synchronisation.
 #include <float.h>
 
 #include "common.hpp"

@@ -607,11 +607,16 @@ __global__ void __launch_bounds__(kThreads) residual_kernel(const double* __rest
 // One pick: score_j = ||Res^T M(:, j)|| / ||M(:, j)|| over unpicked columns with
 // ||M(:, j)|| > 0 (Res = M before the first pick), argmax, append to K.
 // With XL, M (ld p | 1, odd: conflict-free column walks) and Res are read
-// from LDS copies; every sum keeps the order of the global version.
+// from LDS copies; with PAR as well, the n^2 dot products Res(:, c)^T M(:, j)
+// are spread over the threads into an LDS table before thread j sums their
+// squares.  Every sum keeps the order of the global version.
 __host__ __device__ constexpr bool xray_in_lds(int p, int n) {
     return (size_t)((p | 1) + p) * n * sizeof(double) <= kLdsCap;
 }
-template <bool XL>
+__host__ __device__ constexpr bool xray_pairs_in_lds(int p, int n) {
+    return (size_t)((p | 1) + p + n) * n * sizeof(double) <= kLdsCap;
+}
+template <bool XL, bool PAR = false>
 __global__ void __launch_bounds__(kThreads) xray_pick_kernel(const double* __restrict__ M, int p, int n, int ldm,
                                                              const double* __restrict__ Res, int t, int* K,
                                                              int* state) {
@@ -630,6 +635,19 @@ __global__ void __launch_bounds__(kThreads) xray_pick_kernel(const double* __res
         }
         __syncthreads();
     }
+    double* dt = xr_lds + (size_t)(lm + p) * n;       // PAR: d(c, j) at c n + j
+    if constexpr (PAR) {
+        for (int e = threadIdx.x; e < n * n; e += kThreads) {
+            const int c = e / n, jj = e - c * n;
+            const double* rc = Rr + (int64_t)c * p;
+            const double* mj = Mm + (int64_t)jj * lm;
+            double d = 0.0;
+#pragma unroll 4
+            for (int i = 0; i < p; ++i) d += rc[i] * mj[i];
+            dt[e] = d;
+        }
+        __syncthreads();
+    }
     const int j = threadIdx.x;
     double score = -DBL_MAX;
     if (j < n) {
@@ -641,10 +659,15 @@ __global__ void __launch_bounds__(kThreads) xray_pick_kernel(const double* __res
         if (!used && mn > 0.0) {
             double s2 = 0.0;
             for (int c = 0; c < n; ++c) {
-                const double* rc = Rr + (int64_t)c * p;
-                double d = 0.0;
+                double d;
+                if constexpr (PAR) {
+                    d = dt[c * n + j];
+                } else {
+                    const double* rc = Rr + (int64_t)c * p;
+                    d = 0.0;
 #pragma unroll 4
-                for (int i = 0; i < p; ++i) d += rc[i] * mj[i];
+                    for (int i = 0; i < p; ++i) d += rc[i] * mj[i];
+                }
                 s2 += d * d;
             }
             score = __builtin_sqrt(s2) / __builtin_sqrt(mn);
@@ -837,18 +860,23 @@ int select_xray_impl(const double* M, int p, int n, int ldm, int r, int* K, int*
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, state, 2);
     TSNMF_LAUNCH_CHECK();
     const int64_t pn = (int64_t)p * n;
+    const bool xp = xray_pairs_in_lds(p, n);
     const bool xl = xray_in_lds(p, n);
-    const size_t xl_lds = (size_t)((p | 1) + p) * n * sizeof(double);
+    const size_t xl_lds = (size_t)((p | 1) + p + (xp ? n : 0)) * n * sizeof(double);
     if (xl && xl_lds > 65536)
-        TSNMF_HIP(hipFuncSetAttribute((const void*)xray_pick_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)xl_lds));
+        TSNMF_HIP(hipFuncSetAttribute(xp ? (const void*)xray_pick_kernel<true, true>
+                                         : (const void*)xray_pick_kernel<true, false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)xl_lds));
     hipLaunchKernelGGL(copy_matrix_kernel, dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, stream, M, p, n, ldm,
                        Res);
     TSNMF_LAUNCH_CHECK();
     for (int t = 0; t < r && t < n; ++t) {
-        if (xl)
-            hipLaunchKernelGGL(xray_pick_kernel<true>, dim3(1), dim3(kThreads), xl_lds, stream, M, p, n, ldm, Res, t, K,
-                               state);
+        if (xp)
+            hipLaunchKernelGGL((xray_pick_kernel<true, true>), dim3(1), dim3(kThreads), xl_lds, stream, M, p, n, ldm,
+                               Res, t, K, state);
+        else if (xl)
+            hipLaunchKernelGGL((xray_pick_kernel<true, false>), dim3(1), dim3(kThreads), xl_lds, stream, M, p, n, ldm,
+                               Res, t, K, state);
         else
             hipLaunchKernelGGL(xray_pick_kernel<false>, dim3(1), dim3(kThreads), 0, stream, M, p, n, ldm, Res, t, K,
                                state);
